@@ -1,0 +1,287 @@
+/*
+ * mgrav -- gravity interaction lists on one AMD MI355X (gfx950).
+ *
+ * C ABI of the data-parallel core of the PKDGRAV3 gravity solver
+ * (Potter, Stadel & Teyssier, arXiv:1609.08621): evaluation of per-bucket
+ * interaction lists -- softened particle-particle (PP) and particle-cell
+ * (PC) multipole interactions with moments to 4th order -- plus the Ewald
+ * correction of the periodic box, for the particles of the active sink
+ * buckets.  The paper describes the problem and method in Sec. 3.1 (tree,
+ * opening radius, interaction lists, multipole order, precision, Ewald),
+ * Sec. 3.2 (active particles of individual time steps) and Sec. 3.3 (the
+ * split of work between tree walk and interaction evaluation).
+ *
+ * Conventions used by every call:
+ *   - Units: G = 1.  Potential of a softened point mass m at distance r is
+ *     -m / sqrt(r^2 + eps^2) (Plummer softening).
+ *   - Particles are in tree order: every cell owns the contiguous range
+ *     [cell_first[c], cell_first[c] + cell_count[c]).
+ *   - Periodic images: id 0 is the box itself, ids 1..26 the replicas
+ *     shifted by (ix, iy, iz) * L with (ix, iy, iz) in {-1,0,1}^3 \ {0},
+ *     enumerated in lexicographic order (ix slowest).
+ *   - Packed moments of a cell (32 doubles, about the cell's centre of
+ *     mass, raw i.e. not trace-free): [0] mass; [1..6] order 2
+ *     (xx xy xz yy yz zz); [7..16] order 3 (xxx xxy xxz xyy xyz xzz yyy
+ *     yyz yzz zzz); [17..31] order 4 (xxxx xxxy xxxz xxyy xxyz xxzz xyyy
+ *     xyyz xyzz xzzz yyyy yyyz yyzz yzzz zzzz), each component being
+ *     sum_j m_j prod_a (x_j - X)_a.  The dipole vanishes about the centre
+ *     of mass and is not stored.
+ *   - Every call returns an mgrav_status; nothing else crosses the ABI (no
+ *     exceptions, no abort).  After a failure mgrav_last_error() holds a
+ *     message until the next call on the same context.
+ *   - "device" pointers are HIP device (HBM) addresses on the context's
+ *     GPU, "host" pointers are ordinary CPU memory.  Memory passed in is
+ *     borrowed: the library never frees it, and never allocates device
+ *     memory itself (the caller provides a workspace).
+ */
+#ifndef MGRAV_H
+#define MGRAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGRAV_VERSION_MAJOR 0
+#define MGRAV_VERSION_MINOR 1
+
+/* Largest bucket (leaf) the device kernels accept; the paper's optimum
+ * bucket size is about 16 (Sec. 3.1). */
+#define MGRAV_MAX_BUCKET 16
+/* Largest particle count: PP list entries pack a particle index in 27 bits. */
+#define MGRAV_MAX_PARTICLES (1LL << 27)
+
+typedef enum {
+    MGRAV_OK = 0,
+    MGRAV_ERR_INVALID_ARG = 1, /* bad scalar argument or null pointer      */
+    MGRAV_ERR_BAD_TREE = 2,    /* tree inconsistent (found on the device)  */
+    MGRAV_ERR_BAD_LIST = 3,    /* list entry out of range / not a leaf     */
+    MGRAV_ERR_DEVICE = 4,      /* a HIP runtime call failed                */
+    MGRAV_ERR_NO_MEMORY = 5,   /* workspace smaller than required          */
+    MGRAV_ERR_TIMEOUT = 6,     /* mgrav_wait deadline passed               */
+    MGRAV_ERR_STATE = 7,       /* call out of order (e.g. compute before bind) */
+    MGRAV_ERR_NOT_TRAINED = 8  /* surrogate Ewald requested without weights */
+} mgrav_status;
+
+typedef struct mgrav_ctx mgrav_ctx;
+
+/* Version as major * 1000 + minor. */
+int mgrav_version(void);
+
+/* Static text for a status code. */
+const char *mgrav_status_string(mgrav_status s);
+
+/* Message of the last failed call on ctx ("" if none).  Valid until the
+ * next call on ctx.  ctx may be NULL (then the message of the last failed
+ * mgrav_create or host-side call of this thread). */
+const char *mgrav_last_error(const mgrav_ctx *ctx);
+
+/* Create a context on HIP device `device`; all work is enqueued on
+ * `hip_stream` (a hipStream_t, NULL = the default stream).  A context is
+ * not thread-safe; use one per stream. */
+mgrav_status mgrav_create(int device, void *hip_stream, mgrav_ctx **out);
+
+/* Release the context (host resources only; waits for its stream). */
+void mgrav_destroy(mgrav_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
+/* Host-side input preparation: tree build and checklist walk.         */
+/* These run on the CPU (OpenMP), on host pointers, and produce the    */
+/* tree and interaction lists that the device calls consume.           */
+/* ------------------------------------------------------------------ */
+
+/* Binary tree of Sec. 3.1: cells bisect the longest side of their
+ * geometric box at its midpoint (two equal-volume children; lowest axis
+ * index on ties; coordinates >= midpoint go to the upper child; an empty
+ * half shrinks the box and bisection repeats; after 64 halvings on a path
+ * cells split by index halves).  The root is [0, L)^3 when L > 0 and the
+ * particles' bounding box when L == 0.  Leaves (buckets) hold at most
+ * `bucket` particles.  Cells are numbered node-left-right; within a cell
+ * particles keep their input order.  Per cell: centre of mass, tight
+ * bounding box, b_max = largest distance of a particle from the centre of
+ * mass, packed moments.
+ *   pos  [n][3], mass [n]: input order (host).
+ *   Outputs (host, caller-allocated with room for `cap` cells; 2n cells
+ *   always suffice): perm[n] (input index of the k-th particle in tree
+ *   order), cell_first[cap], cell_count[cap], child[cap][2] (-1 = leaf),
+ *   com[cap][3], bmax[cap], bbox[cap][6] (lo xyz, hi xyz), mom[cap][32],
+ *   bucket_cell[cap] (cell of the b-th leaf in order).
+ *   *n_cell and *n_bucket receive the counts.
+ * Errors: INVALID_ARG for n < 1, bucket outside 1..MGRAV_MAX_BUCKET,
+ * non-finite input, L > 0 with a coordinate outside [0, L), non-positive
+ * mass, or cap too small. */
+mgrav_status mgrav_tree_build_host(int64_t n, const double *pos, const double *mass, double L,
+                                   int bucket, int64_t cap, int64_t *perm, int64_t *cell_first,
+                                   int32_t *cell_count, int32_t *child, double *com,
+                                   double *bmax, double *bbox, double *mom,
+                                   int32_t *bucket_cell, int64_t *n_cell, int64_t *n_bucket);
+
+/* Bucket-sink checklist walk (Sec. 3.1).  For every bucket S the
+ * checklist starts with the root cell seen through images 0..n_images-1;
+ * entries are taken from the front and a source cell C seen through
+ * image n becomes
+ *   PC  if |X_C + n L - X_S| > b_max,C / theta + b_max,S and the
+ *       bounding boxes (C shifted by n L) are at least 2 eps apart,
+ *   PP  otherwise if C is a leaf,
+ *   and is otherwise opened: its two children are appended to the end.
+ * Pass 1 (mgrav_lists_count_host) writes CSR offsets pp_off[n_bucket+1]
+ * and pc_off[n_bucket+1]; pass 2 (mgrav_lists_fill_host) fills
+ * pp_src/pc_src (source cell index) and pp_img/pc_img (image id) in
+ * checklist order.  All arrays are host memory; tree arrays as produced
+ * by mgrav_tree_build_host.  n_images is 1 (open, L = 0) or 27.
+ * Errors: INVALID_ARG for theta <= 0, eps < 0, n_images not 1 or 27, or
+ * n_images 27 with L <= 0. */
+mgrav_status mgrav_lists_count_host(int64_t n_bucket, const int32_t *bucket_cell,
+                                    const int32_t *child, const double *com, const double *bmax,
+                                    const double *bbox, double theta, double eps, double L,
+                                    int n_images, int64_t *pp_off, int64_t *pc_off);
+mgrav_status mgrav_lists_fill_host(int64_t n_bucket, const int32_t *bucket_cell,
+                                   const int32_t *child, const double *com, const double *bmax,
+                                   const double *bbox, double theta, double eps, double L,
+                                   int n_images, const int64_t *pp_off, const int64_t *pc_off,
+                                   int32_t *pp_src, uint8_t *pp_img, int32_t *pc_src,
+                                   uint8_t *pc_img);
+
+/* ------------------------------------------------------------------ */
+/* Device-side evaluation.                                             */
+/* ------------------------------------------------------------------ */
+
+/* The problem: particles in tree order, the tree and the per-bucket
+ * interaction lists, all in DEVICE memory (borrowed until the next
+ * mgrav_bind or mgrav_destroy).  Scalars are host values. */
+typedef struct {
+    int64_t n;               /* particles (1 .. MGRAV_MAX_PARTICLES)          */
+    const double *pos;       /* [n][3] positions, tree order                  */
+    const double *mass;      /* [n] masses (> 0)                              */
+    double eps;              /* Plummer softening (> 0)                       */
+    double theta;            /* opening angle the lists were built with (> 0) */
+    double box_L;            /* periodic box side; 0 = open boundaries         */
+    int n_images;            /* 1 (open) or 27 (periodic: box + 26 replicas)  */
+    int64_t n_cell;          /* cells of the tree                             */
+    int64_t n_bucket;        /* leaves (buckets)                              */
+    const int64_t *cell_first; /* [n_cell]                                    */
+    const int32_t *cell_count; /* [n_cell]                                    */
+    const int32_t *child;      /* [n_cell][2], -1 for leaves                  */
+    const double *com;         /* [n_cell][3] centres of mass                 */
+    const double *bbox;        /* [n_cell][6] bounding boxes (lo xyz, hi xyz) */
+    const double *mom;         /* [n_cell][32] packed moments (see above)     */
+    const int32_t *bucket_cell;/* [n_bucket] cell of each bucket              */
+    const int64_t *pp_off;     /* [n_bucket+1] CSR offsets of the PP lists    */
+    const int32_t *pp_src;     /* [n_pp] source leaf cell                     */
+    const uint8_t *pp_img;     /* [n_pp] image id                             */
+    const int64_t *pc_off;     /* [n_bucket+1] CSR offsets of the PC lists    */
+    const int32_t *pc_src;     /* [n_pc] source cell                          */
+    const uint8_t *pc_img;     /* [n_pc] image id                             */
+    int64_t n_pp;              /* = pp_off[n_bucket] (host copy)              */
+    int64_t n_pc;              /* = pc_off[n_bucket] (host copy)              */
+} mgrav_problem;
+
+/* Device workspace the caller must provide to mgrav_bind for `p`. */
+mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
+
+/* Bind a problem: checks the scalar arguments on the host, then enqueues
+ * on the stream the staging kernels that
+ *   (1) store every particle as float offsets from its bucket's centre
+ *       (the centre itself stays in double precision) and its mass,
+ *   (2) convert each cell's moments into the float coefficients of the
+ *       order-4 PC expansion,
+ *   (3) turn every list entry into a float offset between the source (a
+ *       bucket centre for PP, a centre of mass for PC, plus the image
+ *       shift) and the sink bucket's centre, computed in double.
+ * Indices in the tree and lists are checked on the device; a bad entry is
+ * neutralised (never dereferenced) and reported by the next mgrav_wait as
+ * BAD_TREE or BAD_LIST.  `workspace` is a device buffer of at least
+ * mgrav_workspace_size() bytes, 256-byte aligned, owned by the caller and
+ * borrowed until the next bind or destroy.  Re-binding is allowed at any
+ * time after the previous work on the stream. */
+mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace, size_t bytes);
+
+/* Ewald correction of the periodic box (Sec. 3.1): a multipole expansion
+ * of the root cell's field in the Ewald kernel psi, evaluated in double
+ * precision at every active particle.  psi is the periodic potential of a
+ * unit mass (neutralising background, zero mean) minus the 27 nearest
+ * images' Newtonian potentials:
+ *   psi(r) = sum_{|n|_inf<=1} erf(a|r-nL|)/|r-nL|
+ *          - sum_{1<|n|_inf<=real_layers} erfc(a|r-nL|)/|r-nL|
+ *          - 1/(pi L^3) sum_{0<|h|^2<=h2max} exp(-pi^2 h^2/(a L)^2) ... (with
+ *            a = alpha / L and wave vectors 2 pi h / L)
+ *          + pi / (alpha^2 L).
+ * The correction at particle x from root moments M_k about X is
+ *   phi = sum_k (-1)^k / k!  M_k . d^k psi(x - X),  acc = -grad phi,
+ * with k in {0} (order 0), {0, 2} (order 2) or {0, 2, 3, 4} (order 4;
+ * the paper's "5th order": kernel derivatives through order 5 in the
+ * force).  mode NONE switches the correction off (open boundaries need
+ * nothing); EXACT uses the sums above.  SURROGATE uses a trained network
+ * (mgrav_mlp_*) for psi; SURROGATE without weights fails NOT_TRAINED. */
+typedef enum {
+    MGRAV_EWALD_NONE = 0,
+    MGRAV_EWALD_EXACT = 1,
+    MGRAV_EWALD_SURROGATE = 2
+} mgrav_ewald_mode;
+
+typedef struct {
+    int mode;          /* mgrav_ewald_mode                                 */
+    double alpha;      /* Gaussian split in units of 1/L (e.g. 2.6)        */
+    int real_layers;   /* |n|_inf <= real_layers in real space (>= 1)      */
+    int h2max;         /* k-space terms with 0 < |h|^2 <= h2max (0..64)    */
+    int order;         /* 0, 2 or 4 (moments of the root used)             */
+    int top_cells;     /* surrogate: 1 = root monopole, or 8 / 64 cells    */
+} mgrav_ewald;
+
+/* Defaults after bind: EXACT with alpha 2.6, real_layers 1, h2max 10,
+ * order 4 when box_L > 0; NONE when open. */
+mgrav_status mgrav_set_ewald(mgrav_ctx *ctx, const mgrav_ewald *cfg);
+
+/* Active particles of an individual-time-step substep (Sec. 3.2): only
+ * buckets holding at least one active particle are evaluated, and only
+ * active particles' outputs are written (inactive entries keep their
+ * values).  active: device [n] uint8 (non-zero = active), read at every
+ * mgrav_compute (the caller may change its contents between calls), or
+ * NULL = all particles active. */
+mgrav_status mgrav_set_active(mgrav_ctx *ctx, const uint8_t *active_dev);
+
+/* Parts of the evaluation, for mgrav_compute_parts. */
+#define MGRAV_PART_PP 1
+#define MGRAV_PART_PC 2
+#define MGRAV_PART_EWALD 4
+#define MGRAV_PART_ALL 7
+
+/* Evaluate the bound lists: acc[3][n] (SoA: all x, then all y, then all
+ * z) and pot[n], float, tree order, device memory.  The PP and PC sums
+ * are computed in float with float accumulation; the Ewald correction in
+ * double, added to the float sums in double and rounded once.  The self
+ * pair (i, image 0) is excluded; a particle's own replicas are included.
+ * Asynchronous: returns after enqueueing; use mgrav_wait.  The first call
+ * after bind (or with new output pointers) captures a HIP graph of the
+ * launch sequence; later calls replay it. */
+mgrav_status mgrav_compute(mgrav_ctx *ctx, float *acc, float *pot);
+
+/* As mgrav_compute, restricted to the parts in `parts` (MGRAV_PART_*). */
+mgrav_status mgrav_compute_parts(mgrav_ctx *ctx, int parts, float *acc, float *pot);
+
+/* Counters and timings of the last compute. */
+typedef struct {
+    int64_t n_pp_interactions;   /* sink particle x source particle x image  */
+    int64_t n_pc_interactions;   /* sink particle x source cell x image      */
+    int64_t n_active_buckets;
+    int64_t n_active_particles;
+    double ms_total;             /* stream time of the last compute          */
+    double ms_interact;          /* PP + PC kernel of the last compute       */
+    double ms_ewald;             /* Ewald kernels of the last compute        */
+    int graph_replay;            /* 1: launched from captured HIP graphs     */
+} mgrav_stats;
+
+/* Wait for the context's work with a watchdog: polls the completion event
+ * until `timeout_s` (<= 0: wait forever) passes, then returns TIMEOUT and
+ * marks the context failed (it must be re-bound).  Reports device-side
+ * validation failures from the last bind (BAD_TREE / BAD_LIST).  stats
+ * may be NULL. */
+mgrav_status mgrav_wait(mgrav_ctx *ctx, double timeout_s, mgrav_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGRAV_H */

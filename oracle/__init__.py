@@ -63,6 +63,8 @@ _D = ctypes.c_double
 
 def _declare(L):
     L.orc_init.argtypes = []
+    L.orc_num_threads.restype = _I
+    L.orc_num_threads.argtypes = []
     L.orc_image_shift.argtypes = [_I, _D, _P]
     L.orc_tree_build.restype = _I64
     L.orc_tree_build.argtypes = [_I64, _P, _P, _D, _I, _I64, _P, _P, _P, _P, _P, _P, _P,
@@ -129,6 +131,10 @@ class Lists:
     pc_src: np.ndarray
     pc_img: np.ndarray
     n_images: int
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def image_shift(img: int, L: float) -> np.ndarray:

@@ -40,8 +40,21 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define ORC_SQRT_PI 1.7724538509055160273
 #define ORC_PI 3.14159265358979323846
+
+/* Threads the OpenMP loops below use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Periodic images: id 0 is the box itself, ids 1..26 the neighbouring  */

@@ -1,0 +1,353 @@
+"""mgrav: PKDGRAV3 gravity interaction lists on one AMD MI355X (gfx950).
+
+Thin Python binding of the C ABI declared in ``include/mgrav.h``
+(arXiv:1609.08621, Sec. 3.1-3.3).  This module only marshals arguments:
+torch tensors provide device memory and the HIP stream, and every step of
+the evaluation runs in the HIP kernels of ``libmgrav.so``.  There is no CPU
+fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgrav.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -m paper_1609_08621_amd.build` "
+        "(the HIP extension is required, there is no fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+OK, ERR_INVALID_ARG, ERR_BAD_TREE, ERR_BAD_LIST, ERR_DEVICE, ERR_NO_MEMORY, \
+    ERR_TIMEOUT, ERR_STATE, ERR_NOT_TRAINED = range(9)
+PART_PP, PART_PC, PART_EWALD, PART_ALL = 1, 2, 4, 7
+EWALD_NONE, EWALD_EXACT, EWALD_SURROGATE = 0, 1, 2
+MAX_BUCKET = 16
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", _I64), ("pos", _P), ("mass", _P), ("eps", _D), ("theta", _D), ("box_L", _D),
+        ("n_images", _I), ("n_cell", _I64), ("n_bucket", _I64), ("cell_first", _P),
+        ("cell_count", _P), ("child", _P), ("com", _P), ("bbox", _P), ("mom", _P),
+        ("bucket_cell", _P), ("pp_off", _P), ("pp_src", _P), ("pp_img", _P), ("pc_off", _P),
+        ("pc_src", _P), ("pc_img", _P), ("n_pp", _I64), ("n_pc", _I64),
+    ]
+
+
+class EwaldConfig(ctypes.Structure):
+    _fields_ = [("mode", _I), ("alpha", _D), ("real_layers", _I), ("h2max", _I),
+                ("order", _I), ("top_cells", _I)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_pp_interactions", _I64), ("n_pc_interactions", _I64),
+                ("n_active_buckets", _I64), ("n_active_particles", _I64),
+                ("ms_total", _D), ("ms_interact", _D), ("ms_ewald", _D),
+                ("graph_replay", _I)]
+
+
+def _declare():
+    L = _lib
+    L.mgrav_version.restype = _I
+    L.mgrav_status_string.restype = ctypes.c_char_p
+    L.mgrav_status_string.argtypes = [_I]
+    L.mgrav_last_error.restype = ctypes.c_char_p
+    L.mgrav_last_error.argtypes = [_P]
+    L.mgrav_create.restype = _I
+    L.mgrav_create.argtypes = [_I, _P, ctypes.POINTER(_P)]
+    L.mgrav_destroy.restype = None
+    L.mgrav_destroy.argtypes = [_P]
+    L.mgrav_tree_build_host.restype = _I
+    L.mgrav_tree_build_host.argtypes = [_I64, _P, _P, _D, _I, _I64] + [_P] * 11
+    L.mgrav_lists_count_host.restype = _I
+    L.mgrav_lists_count_host.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P]
+    L.mgrav_lists_fill_host.restype = _I
+    L.mgrav_lists_fill_host.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P,
+                                        _P, _P, _P, _P]
+    L.mgrav_workspace_size.restype = _I
+    L.mgrav_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
+    L.mgrav_bind.restype = _I
+    L.mgrav_bind.argtypes = [_P, ctypes.POINTER(Problem), _P, ctypes.c_size_t]
+    L.mgrav_set_ewald.restype = _I
+    L.mgrav_set_ewald.argtypes = [_P, ctypes.POINTER(EwaldConfig)]
+    L.mgrav_set_active.restype = _I
+    L.mgrav_set_active.argtypes = [_P, _P]
+    L.mgrav_compute.restype = _I
+    L.mgrav_compute.argtypes = [_P, _P, _P]
+    L.mgrav_compute_parts.restype = _I
+    L.mgrav_compute_parts.argtypes = [_P, _I, _P, _P]
+    L.mgrav_wait.restype = _I
+    L.mgrav_wait.argtypes = [_P, _D, ctypes.POINTER(Stats)]
+
+
+_declare()
+
+# Every symbol include/mgrav.h declares (checked by the CPU tests).
+EXPORTS = (
+    "mgrav_version", "mgrav_status_string", "mgrav_last_error", "mgrav_create",
+    "mgrav_destroy", "mgrav_tree_build_host", "mgrav_lists_count_host",
+    "mgrav_lists_fill_host", "mgrav_workspace_size", "mgrav_bind", "mgrav_set_ewald",
+    "mgrav_set_active", "mgrav_compute", "mgrav_compute_parts", "mgrav_wait",
+)
+
+
+class MgravError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        name = _lib.mgrav_status_string(status).decode()
+        super().__init__(f"mgrav: {name} ({status}): {msg}")
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = _lib.mgrav_last_error(ctx).decode(errors="replace")
+        raise MgravError(status, msg)
+
+
+def version() -> int:
+    return _lib.mgrav_version()
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Host-side input preparation (tree build and checklist walk on the CPU)
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Tree:
+    """Host arrays of a tree, layout as in include/mgrav.h."""
+
+    perm: np.ndarray
+    cell_first: np.ndarray
+    cell_count: np.ndarray
+    child: np.ndarray
+    com: np.ndarray
+    bmax: np.ndarray
+    bbox: np.ndarray
+    mom: np.ndarray
+    bucket_cell: np.ndarray
+    box_L: float
+
+    @property
+    def n_cell(self):
+        return int(self.cell_first.shape[0])
+
+    @property
+    def n_bucket(self):
+        return int(self.bucket_cell.shape[0])
+
+
+@dataclasses.dataclass
+class Lists:
+    pp_off: np.ndarray
+    pp_src: np.ndarray
+    pp_img: np.ndarray
+    pc_off: np.ndarray
+    pc_src: np.ndarray
+    pc_img: np.ndarray
+    n_images: int
+
+
+def tree_build(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16) -> Tree:
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = pos.shape[0]
+    cap = 2 * n + 2
+    perm = np.empty(n, np.int64)
+    cf = np.empty(cap, np.int64)
+    cc = np.empty(cap, np.int32)
+    ch = np.empty(2 * cap, np.int32)
+    com = np.empty(3 * cap)
+    bmax = np.empty(cap)
+    bbox = np.empty(6 * cap)
+    mom = np.empty(32 * cap)
+    bc = np.empty(cap, np.int32)
+    nc = np.zeros(1, np.int64)
+    nb = np.zeros(1, np.int64)
+    _check(_lib.mgrav_tree_build_host(n, _ptr(pos), _ptr(mass), float(box_L), int(bucket), cap,
+                                      _ptr(perm), _ptr(cf), _ptr(cc), _ptr(ch), _ptr(com),
+                                      _ptr(bmax), _ptr(bbox), _ptr(mom), _ptr(bc), _ptr(nc),
+                                      _ptr(nb)))
+    c, b = int(nc[0]), int(nb[0])
+    return Tree(perm, cf[:c].copy(), cc[:c].copy(), ch[:2 * c].reshape(c, 2).copy(),
+                com[:3 * c].reshape(c, 3).copy(), bmax[:c].copy(),
+                bbox[:6 * c].reshape(c, 6).copy(), mom[:32 * c].reshape(c, 32).copy(),
+                bc[:b].copy(), float(box_L))
+
+
+def lists_build(tree: Tree, theta: float, eps: float, n_images: Optional[int] = None) -> Lists:
+    if n_images is None:
+        n_images = 27 if tree.box_L > 0 else 1
+    nb = tree.n_bucket
+    pp_off = np.zeros(nb + 1, np.int64)
+    pc_off = np.zeros(nb + 1, np.int64)
+    common = (nb, _ptr(tree.bucket_cell), _ptr(tree.child), _ptr(tree.com), _ptr(tree.bmax),
+              _ptr(tree.bbox), float(theta), float(eps), float(tree.box_L), int(n_images))
+    _check(_lib.mgrav_lists_count_host(*common, _ptr(pp_off), _ptr(pc_off)))
+    pp_src = np.empty(max(1, int(pp_off[-1])), np.int32)
+    pp_img = np.empty(max(1, int(pp_off[-1])), np.uint8)
+    pc_src = np.empty(max(1, int(pc_off[-1])), np.int32)
+    pc_img = np.empty(max(1, int(pc_off[-1])), np.uint8)
+    _check(_lib.mgrav_lists_fill_host(*common, _ptr(pp_off), _ptr(pc_off), _ptr(pp_src),
+                                      _ptr(pp_img), _ptr(pc_src), _ptr(pc_img)))
+    npp, npc = int(pp_off[-1]), int(pc_off[-1])
+    return Lists(pp_off, pp_src[:npp], pp_img[:npp], pc_off, pc_src[:npc], pc_img[:npc],
+                 int(n_images))
+
+
+# --------------------------------------------------------------------------
+# Device side
+# --------------------------------------------------------------------------
+class Context:
+    """One mgrav context on a device and a (torch) HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("mgrav needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        h = _P()
+        _check(_lib.mgrav_create(int(device), _P(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mgrav_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------
+    def upload(self, pos_tree: np.ndarray, mass_tree: np.ndarray, tree, lists, eps: float,
+               theta: float):
+        """Copy particles (tree order), tree and lists to the device and
+        return the device tensors plus a filled Problem (not yet bound)."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+
+        def t(a, dtype=None):
+            a = np.ascontiguousarray(a if dtype is None else a.astype(dtype))
+            return torch.from_numpy(a).to(dev)
+
+        keep = dict(
+            pos=t(pos_tree, np.float64), mass=t(mass_tree, np.float64),
+            cell_first=t(tree.cell_first, np.int64), cell_count=t(tree.cell_count, np.int32),
+            child=t(tree.child, np.int32), com=t(tree.com, np.float64),
+            bbox=t(tree.bbox, np.float64), mom=t(tree.mom, np.float64),
+            bucket_cell=t(tree.bucket_cell, np.int32), pp_off=t(lists.pp_off, np.int64),
+            pp_src=t(lists.pp_src if lists.pp_src.size else np.zeros(1, np.int32), np.int32),
+            pp_img=t(lists.pp_img if lists.pp_img.size else np.zeros(1, np.uint8), np.uint8),
+            pc_off=t(lists.pc_off, np.int64),
+            pc_src=t(lists.pc_src if lists.pc_src.size else np.zeros(1, np.int32), np.int32),
+            pc_img=t(lists.pc_img if lists.pc_img.size else np.zeros(1, np.uint8), np.uint8),
+        )
+        p = Problem()
+        p.n = pos_tree.shape[0]
+        p.eps = float(eps)
+        p.theta = float(theta)
+        p.box_L = float(tree.box_L)
+        p.n_images = int(lists.n_images)
+        p.n_cell = int(tree.cell_first.shape[0])
+        p.n_bucket = int(tree.bucket_cell.shape[0])
+        for name in ("pos", "mass", "cell_first", "cell_count", "child", "com", "bbox", "mom",
+                     "bucket_cell", "pp_off", "pp_src", "pp_img", "pc_off", "pc_src",
+                     "pc_img"):
+            setattr(p, name, keep[name].data_ptr())
+        p.n_pp = int(lists.pp_off[-1])
+        p.n_pc = int(lists.pc_off[-1])
+        torch.cuda.synchronize(dev)
+        return keep, p
+
+    def workspace_size(self, p: Problem) -> int:
+        sz = ctypes.c_size_t(0)
+        _check(_lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)))
+        return int(sz.value)
+
+    def bind(self, p: Problem, tensors: dict, workspace=None):
+        """Bind a problem; allocates the workspace as a torch uint8 tensor
+        unless one is given.  Keeps references to the device tensors."""
+        torch = self._torch
+        nbytes = self.workspace_size(p)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8,
+                                    device=torch.device("cuda", self.device))
+        self._keep = dict(tensors)
+        self._keep["workspace"] = workspace
+        self.problem = p
+        self.n = int(p.n)
+        # inputs were produced on torch's current stream
+        self.stream.wait_stream(torch.cuda.current_stream(torch.device("cuda", self.device)))
+        _check(_lib.mgrav_bind(self._h, ctypes.byref(p), _P(workspace.data_ptr()),
+                               ctypes.c_size_t(workspace.numel())), self._h)
+
+    def set_ewald(self, mode: int = EWALD_EXACT, alpha: float = 2.6, real_layers: int = 1,
+                  h2max: int = 10, order: int = 4, top_cells: int = 1):
+        cfg = EwaldConfig(int(mode), float(alpha), int(real_layers), int(h2max), int(order),
+                          int(top_cells))
+        _check(_lib.mgrav_set_ewald(self._h, ctypes.byref(cfg)), self._h)
+
+    def set_active(self, active_dev=None):
+        self._keep["active"] = active_dev
+        ptr = None if active_dev is None else _P(active_dev.data_ptr())
+        _check(_lib.mgrav_set_active(self._h, ptr), self._h)
+
+    def compute(self, acc, pot, parts: int = PART_ALL):
+        torch = self._torch
+        self.stream.wait_stream(torch.cuda.current_stream(torch.device("cuda", self.device)))
+        _check(_lib.mgrav_compute_parts(self._h, int(parts), _P(acc.data_ptr()),
+                                        _P(pot.data_ptr())), self._h)
+
+    def wait(self, timeout_s: float = 60.0) -> Stats:
+        st = Stats()
+        _check(_lib.mgrav_wait(self._h, float(timeout_s), ctypes.byref(st)), self._h)
+        return st
+
+    def outputs(self):
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        acc = torch.zeros(3 * self.n, dtype=torch.float32, device=dev)
+        pot = torch.zeros(self.n, dtype=torch.float32, device=dev)
+        return acc, pot
+
+
+def solve(ctx: Context, pos_tree, mass_tree, tree, lists, eps: float, theta: float,
+          parts: int = PART_ALL, ewald: Optional[dict] = None, active: Optional[np.ndarray] = None,
+          timeout_s: float = 120.0):
+    """Upload, bind, compute once and return (acc [n,3], pot [n], stats) as
+    numpy arrays in tree order."""
+    torch = ctx._torch
+    tensors, p = ctx.upload(pos_tree, mass_tree, tree, lists, eps, theta)
+    ctx.bind(p, tensors)
+    if ewald is not None:
+        ctx.set_ewald(**ewald)
+    if active is not None:
+        act = torch.from_numpy(np.ascontiguousarray(active, dtype=np.uint8)).to(
+            torch.device("cuda", ctx.device))
+        ctx.set_active(act)
+    acc, pot = ctx.outputs()
+    ctx.compute(acc, pot, parts)
+    st = ctx.wait(timeout_s)
+    a = acc.cpu().numpy().reshape(3, -1).T.copy()
+    return a, pot.cpu().numpy().copy(), st

@@ -1,0 +1,42 @@
+"""Build libmgrav.so in-tree: HIP kernels for gfx950 plus the host-side
+tree builder (g++ with OpenMP).  Run ``python -m paper_1609_08621_amd.build``."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libmgrav.so")
+ARCH = os.environ.get("MGRAV_OFFLOAD_ARCH", "gfx950")
+
+# Packed FP32 instructions stay disabled in all device code.
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wall", "-Wno-unused-function"]
+
+
+def _run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose: bool = True) -> str:
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    tree_o = os.path.join(bdir, "tree_host.o")
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-ffp-contract=off", "-Wall",
+          "-c", os.path.join(CSRC, "tree_host.cpp"), "-o", tree_o])
+    dev_o = os.path.join(bdir, "mgrav.o")
+    _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "mgrav.hip"), "-o", dev_o])
+    tmp = LIB + ".tmp"
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, dev_o, tree_o,
+          "-lgomp"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,1364 @@
+// mgrav: device evaluation of PKDGRAV3 interaction lists on MI355X (gfx950).
+//
+// Paper: Potter, Stadel & Teyssier, arXiv:1609.08621.  Sec. 3.1 defines
+// the tree, the PP and PC interaction lists, the multipole order (moments
+// to 4th order), single-precision interactions and the Ewald correction;
+// Sec. 3.3 assigns PP, PC and Ewald work to the GPU; Sec. 3.2 restricts
+// work to the active particles of a substep.
+//
+// Launch sequence of one mgrav_compute (captured in a HIP graph):
+//   k_reset        control block (queue head, counters)
+//   k_select       active buckets -> work queue, interaction counts
+//   k_interact     persistent: PP + PC for every queued sink bucket
+//   k_ewald_setup  root coefficients and k-space table (periodic only)
+//   k_ewald        FP64 Ewald correction per active particle, added to
+//                  the float tree sums in double and rounded once
+// mgrav_bind enqueues the staging kernels k_stage_* once per problem.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <thread>
+
+#include "../../include/mgrav.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBucket = MGRAV_MAX_BUCKET;  // 16 sinks per work item
+constexpr int kRec = 44;                   // floats per staged cell record
+constexpr int kChunk = 64;                 // PP entries expanded per LDS fill
+constexpr int kLdsSrc = kChunk * kBucket;  // source particles per fill
+constexpr int kMaxH2 = 64;                 // largest k-space cut-off |h|^2
+constexpr int kMaxHalfK = 1054;            // half-space wave vectors with |h|^2 <= 64
+constexpr int kErrTree = 1, kErrList = 2, kErrParticle = 4;
+
+// Control block at the start of the workspace.
+struct Control {
+    int err;
+    int n_items;
+    int head;
+    int pad;
+    unsigned long long n_pp_int;
+    unsigned long long n_pc_int;
+    unsigned long long n_active_p;
+    unsigned long long n_active_b;
+};
+
+// Image shifts in units of L: id 0 the box, 1..26 lexicographic {-1,0,1}^3.
+__constant__ signed char c_shift[27][3] = {
+    {0, 0, 0},   {-1, -1, -1}, {-1, -1, 0}, {-1, -1, 1}, {-1, 0, -1}, {-1, 0, 0}, {-1, 0, 1},
+    {-1, 1, -1}, {-1, 1, 0},   {-1, 1, 1},  {0, -1, -1}, {0, -1, 0},  {0, -1, 1}, {0, 0, -1},
+    {0, 0, 1},   {0, 1, -1},   {0, 1, 0},   {0, 1, 1},   {1, -1, -1}, {1, -1, 0}, {1, -1, 1},
+    {1, 0, -1},  {1, 0, 0},    {1, 0, 1},   {1, 1, -1},  {1, 1, 0},   {1, 1, 1}};
+
+// Per-bucket work descriptor written by the staging kernels; every range
+// in it has been checked against the array it indexes.
+struct BucketWork {
+    int first;           // first sink particle
+    int nsink;           // sink particles (0 = bucket skipped)
+    int self;            // own bucket is on the PP list at image 0
+    int nsrc;            // source particles over the PP list
+    long long pp0, pp1;  // PP entries [pp0, pp1)
+    long long pc0, pc1;  // PC entries [pc0, pc1)
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace segments (byte offsets from the workspace base).
+struct Layout {
+    size_t ctl, pdat, work, items, cellrec, ppent, pcent, ewald, total;
+};
+
+Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, int64_t n_pc) {
+    Layout l{};
+    size_t o = 0;
+    l.ctl = o;
+    o += align256(sizeof(Control));
+    l.pdat = o;
+    o += align256(sizeof(float4) * n);
+    l.work = o;
+    o += align256(sizeof(BucketWork) * n_bucket);
+    l.items = o;
+    o += align256(sizeof(int) * n_bucket);
+    l.cellrec = o;
+    o += align256(sizeof(float) * kRec * n_cell);
+    l.ppent = o;
+    o += align256(sizeof(float4) * (n_pp > 0 ? n_pp : 1));
+    l.pcent = o;
+    o += align256(sizeof(float4) * (n_pc > 0 ? n_pc : 1));
+    l.ewald = o;
+    o += align256(sizeof(double) * (64 + 8 * kMaxHalfK));
+    l.total = o;
+    return l;
+}
+
+// ---------------------------------------------------------------------
+// Staging (mgrav_bind)
+// ---------------------------------------------------------------------
+struct StageArgs {
+    int64_t n, n_cell, n_bucket, n_pp, n_pc;
+    int n_images;
+    double L;
+    const double* __restrict__ pos;
+    const double* __restrict__ mass;
+    const int64_t* __restrict__ cell_first;
+    const int32_t* __restrict__ cell_count;
+    const int32_t* __restrict__ child;
+    const double* __restrict__ com;
+    const double* __restrict__ bbox;
+    const double* __restrict__ mom;
+    const int32_t* __restrict__ bucket_cell;
+    const int64_t* __restrict__ pp_off;
+    const int32_t* __restrict__ pp_src;
+    const uint8_t* __restrict__ pp_img;
+    const int64_t* __restrict__ pc_off;
+    const int32_t* __restrict__ pc_src;
+    const uint8_t* __restrict__ pc_img;
+    Control* ctl;
+    float4* pdat;
+    BucketWork* work;
+    float* cellrec;
+    float4* ppent;
+    float4* pcent;
+};
+
+__global__ void k_init_control(Control* ctl) {
+    if (threadIdx.x == 0) {
+        ctl->err = 0;
+        ctl->n_items = 0;
+        ctl->head = 0;
+        ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
+    }
+}
+
+// Is cell c a valid bucket (leaf with 1..16 particles inside [0, n))?
+__device__ bool valid_bucket(const StageArgs& a, int64_t c, int64_t* first, int* cnt) {
+    if (c < 0 || c >= a.n_cell) return false;
+    if (a.child[2 * c] >= 0) return false;
+    const int64_t f = a.cell_first[c];
+    const int k = a.cell_count[c];
+    if (k < 1 || k > kBucket || f < 0 || f + k > a.n) return false;
+    *first = f;
+    *cnt = k;
+    return true;
+}
+
+__device__ void bbox_centre(const double* __restrict__ bbox, int64_t c, double C[3]) {
+    for (int d = 0; d < 3; ++d) C[d] = 0.5 * (bbox[6 * c + d] + bbox[6 * c + 3 + d]);
+}
+
+// (1) particles: float offset from the bucket's bounding-box centre + mass.
+__global__ void k_stage_particles(StageArgs a) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t b = t / kBucket;
+    const int k = int(t % kBucket);
+    if (b >= a.n_bucket) return;
+    const int64_t c = a.bucket_cell[b];
+    int64_t first = 0;
+    int cnt = 0;
+    if (!valid_bucket(a, c, &first, &cnt)) {
+        if (k == 0) {
+            atomicOr(&a.ctl->err, kErrTree);
+            a.work[b].first = 0;
+            a.work[b].nsink = 0;
+        }
+        return;
+    }
+    double C[3];
+    bbox_centre(a.bbox, c, C);
+    if (k < cnt) {
+        const int64_t p = first + k;
+        const double x = a.pos[3 * p], y = a.pos[3 * p + 1], z = a.pos[3 * p + 2];
+        const double m = a.mass[p];
+        if (!(isfinite(x) && isfinite(y) && isfinite(z) && m > 0.0 && isfinite(m)))
+            atomicOr(&a.ctl->err, kErrParticle);
+        a.pdat[p] = make_float4(float(x - C[0]), float(y - C[1]), float(z - C[2]), float(m));
+    }
+    if (k == 0) {
+        a.work[b].first = int(first);
+        a.work[b].nsink = cnt;
+    }
+}
+
+// (2) cells: float coefficients of the order-4 expansion (see pc_terms).
+__global__ void k_stage_cells(StageArgs a) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= a.n_cell) return;
+    const double* m = a.mom + 32 * c;
+    double r[kRec];
+    r[0] = m[0];
+    r[1] = 0.5 * (m[1] + m[4] + m[6]);
+    for (int i = 0; i < 6; ++i) r[2 + i] = 0.5 * m[1 + i];
+    r[8] = -0.5 * (m[7] + m[10] + m[12]);
+    r[9] = -0.5 * (m[8] + m[13] + m[15]);
+    r[10] = -0.5 * (m[9] + m[14] + m[16]);
+    r[11] = 0.125 * (m[17] + m[27] + m[31] + 2.0 * (m[20] + m[22] + m[29]));
+    for (int i = 0; i < 10; ++i) r[12 + i] = -m[7 + i] / 6.0;
+    r[22] = 0.25 * (m[17] + m[20] + m[22]);
+    r[23] = 0.25 * (m[18] + m[23] + m[25]);
+    r[24] = 0.25 * (m[19] + m[24] + m[26]);
+    r[25] = 0.25 * (m[20] + m[27] + m[29]);
+    r[26] = 0.25 * (m[21] + m[28] + m[30]);
+    r[27] = 0.25 * (m[22] + m[29] + m[31]);
+    for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0;
+    r[43] = 0.0;
+    float4* out = reinterpret_cast<float4*>(a.cellrec + kRec * c);
+    for (int i = 0; i < kRec / 4; ++i)
+        out[i] = make_float4(float(r[4 * i]), float(r[4 * i + 1]), float(r[4 * i + 2]),
+                             float(r[4 * i + 3]));
+}
+
+__device__ inline int block_or(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+__device__ inline int block_sum(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// (3a) PP entries: offset between the source bucket's centre (plus image
+// shift) and the sink bucket's centre, in double, rounded to float; the
+// source's first particle and count packed into the fourth word.
+__global__ void __launch_bounds__(kWave) k_stage_pp(StageArgs a) {
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t s = a.bucket_cell[b];
+    const bool sink_ok = s >= 0 && s < a.n_cell;
+    const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
+    const bool range_ok = e0 >= 0 && e0 <= e1 && e1 <= a.n_pp;
+    double C[3] = {0, 0, 0};
+    if (sink_ok) bbox_centre(a.bbox, s, C);
+    int nsrc = 0, self = 0, bad = 0;
+    if (!range_ok || !sink_ok) bad = 1;
+    if (range_ok) {
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            const int64_t src = a.pp_src[e];
+            const int img = a.pp_img[e];
+            int64_t f = 0;
+            int k = 0;
+            float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+            if (sink_ok && img < a.n_images && valid_bucket(a, src, &f, &k)) {
+                double S[3];
+                bbox_centre(a.bbox, src, S);
+                out.x = float(S[0] + c_shift[img][0] * a.L - C[0]);
+                out.y = float(S[1] + c_shift[img][1] * a.L - C[1]);
+                out.z = float(S[2] + c_shift[img][2] * a.L - C[2]);
+                out.w = __uint_as_float(uint32_t(f) | (uint32_t(k) << 27));
+                nsrc += k;
+                if (src == s && img == 0) self = 1;
+            } else {
+                bad = 1;
+            }
+            a.ppent[e] = out;
+        }
+    }
+    bad = block_or(bad);
+    self = block_or(self);
+    nsrc = block_sum(nsrc);
+    if (lane == 0) {
+        if (bad) atomicOr(&a.ctl->err, kErrList);
+        a.work[b].self = self;
+        a.work[b].nsrc = nsrc;
+        a.work[b].pp0 = range_ok ? e0 : 0;
+        a.work[b].pp1 = range_ok ? e1 : 0;
+    }
+}
+
+// (3b) PC entries: offset of the source's centre of mass (plus image
+// shift) from the sink bucket's centre; the cell index in the fourth word.
+__global__ void __launch_bounds__(kWave) k_stage_pc(StageArgs a) {
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t s = a.bucket_cell[b];
+    const bool sink_ok = s >= 0 && s < a.n_cell;
+    const int64_t e0 = a.pc_off[b], e1 = a.pc_off[b + 1];
+    const bool range_ok = e0 >= 0 && e0 <= e1 && e1 <= a.n_pc;
+    double C[3] = {0, 0, 0};
+    if (sink_ok) bbox_centre(a.bbox, s, C);
+    int bad = (!range_ok || !sink_ok) ? 1 : 0;
+    if (range_ok) {
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            const int64_t src = a.pc_src[e];
+            const int img = a.pc_img[e];
+            // an invalid entry becomes a massless cell at the bucket centre
+            float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+            if (sink_ok && src >= 0 && src < a.n_cell && img < a.n_images) {
+                out.x = float(a.com[3 * src] + c_shift[img][0] * a.L - C[0]);
+                out.y = float(a.com[3 * src + 1] + c_shift[img][1] * a.L - C[1]);
+                out.z = float(a.com[3 * src + 2] + c_shift[img][2] * a.L - C[2]);
+                out.w = __int_as_float(int(src));
+            } else {
+                bad = 1;
+            }
+            a.pcent[e] = out;
+        }
+    }
+    bad = block_or(bad);
+    if (lane == 0) {
+        if (bad) atomicOr(&a.ctl->err, kErrList);
+        a.work[b].pc0 = range_ok ? e0 : 0;
+        a.work[b].pc1 = range_ok ? e1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------
+// Per-compute kernels
+// ---------------------------------------------------------------------
+struct RunArgs {
+    int64_t n, n_bucket;
+    const uint8_t* __restrict__ active;
+    Control* ctl;
+    const float4* __restrict__ pdat;
+    const BucketWork* __restrict__ work;
+    int* items;
+    const float* __restrict__ cellrec;
+    const float4* __restrict__ ppent;
+    const float4* __restrict__ pcent;
+    float* __restrict__ acc;  // [3][n]
+    float* __restrict__ pot;  // [n]
+    float eps2;
+    int parts;
+};
+
+__global__ void k_reset(Control* ctl, int n_items_all, int use_mask) {
+    if (threadIdx.x == 0) {
+        ctl->n_items = use_mask ? 0 : n_items_all;
+        ctl->head = 0;
+        ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
+    }
+}
+
+// Active buckets into the work queue (in bucket order when all particles
+// are active) and the interaction counts of the active sinks.
+__global__ void __launch_bounds__(256) k_select(RunArgs a) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    unsigned long long npp = 0, npc = 0, nact = 0, nb = 0;
+    if (b < a.n_bucket) {
+        const BucketWork wk = a.work[b];
+        int na = wk.nsink;
+        if (a.active) {
+            na = 0;
+            for (int k = 0; k < wk.nsink; ++k) na += a.active[wk.first + k] != 0;
+        }
+        if (a.active == nullptr) {
+            a.items[b] = int(b);
+        } else if (na > 0) {
+            const int slot = atomicAdd(&a.ctl->n_items, 1);
+            a.items[slot] = int(b);
+        }
+        if (na > 0) {
+            nact = na;
+            nb = 1;
+            npp = (unsigned long long)na * (unsigned long long)wk.nsrc;
+            npc = (unsigned long long)na * (unsigned long long)(wk.pc1 - wk.pc0);
+        }
+    }
+    // block reduction, one atomic per block
+    __shared__ unsigned long long red[4][256 / kWave];
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        npp += __shfl_xor(npp, o);
+        npc += __shfl_xor(npc, o);
+        nact += __shfl_xor(nact, o);
+        nb += __shfl_xor(nb, o);
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[0][w] = npp;
+        red[1][w] = npc;
+        red[2][w] = nact;
+        red[3][w] = nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s[4] = {0, 0, 0, 0};
+        for (int i = 0; i < int(blockDim.x / kWave); ++i)
+            for (int q = 0; q < 4; ++q) s[q] += red[q][i];
+        if (s[2]) {
+            atomicAdd(&a.ctl->n_pp_int, s[0]);
+            atomicAdd(&a.ctl->n_pc_int, s[1]);
+            atomicAdd(&a.ctl->n_active_p, s[2]);
+            atomicAdd(&a.ctl->n_active_b, s[3]);
+        }
+    }
+}
+
+// Order-4 PC expansion of one cell at one point, float.
+//   R = x - X (sink minus expansion centre), D = R.R + eps^2,
+//   a_n = ((1/r) d/dr)^n D^(-1/2) = (-1)^n (2n-1)!! D^(-(2n+1)/2),
+//   phi = -sum_n a_n P_n(R),  acc = sum_n (a_{n+1} P_n R + a_n grad P_n),
+// with P_0 = M, P_1 = tr(M2)/2, P_2 = R.M2.R/2 - tr(M3).R/2 + tr tr(M4)/8,
+// P_3 = -M3[RRR]/6 + R.tr(M4).R/4, P_4 = M4[RRRR]/24: the Taylor series of
+// the softened potential about the centre of mass, grouped by radial
+// derivative.  The staged record holds the scaled moment combinations
+// r[0]=M, r[1]=trM2/2, r[2..7]=M2/2, r[8..10]=-trM3/2, r[11]=ttrM4/8,
+// r[12..21]=-M3/6, r[22..27]=trM4/4, r[28..42]=M4/24.
+template <typename T, typename Rec>
+__device__ __forceinline__ void multipole_terms(const Rec& r, T x, T y, T z, T& P2, T& P3,
+                                                T& P4, T& g2x, T& g2y, T& g2z, T& g3x, T& g3y,
+                                                T& g3z, T& v4x, T& v4y, T& v4z) {
+    const T xx = x * x, yy = y * y, zz = z * z;
+    const T x2 = x + x, y2 = y + y;
+    const T qxy = x2 * y, qxz = x2 * z, qyz = y2 * z;
+    // order 2 (with the traced parts of orders 3 and 4)
+    const T v2x = r[2] * x + r[3] * y + r[4] * z;
+    const T v2y = r[3] * x + r[5] * y + r[6] * z;
+    const T v2z = r[4] * x + r[6] * y + r[7] * z;
+    P2 = x * (v2x + r[8]) + y * (v2y + r[9]) + z * (v2z + r[10]) + r[11];
+    g2x = v2x + v2x + r[8];
+    g2y = v2y + v2y + r[9];
+    g2z = v2z + v2z + r[10];
+    // order 3 (with the once-traced part of order 4)
+    const T v3x = r[12] * xx + r[15] * yy + r[17] * zz + r[13] * qxy + r[14] * qxz + r[16] * qyz;
+    const T v3y = r[13] * xx + r[18] * yy + r[20] * zz + r[15] * qxy + r[16] * qxz + r[19] * qyz;
+    const T v3z = r[14] * xx + r[19] * yy + r[21] * zz + r[16] * qxy + r[17] * qxz + r[20] * qyz;
+    const T w4x = r[22] * x + r[23] * y + r[24] * z;
+    const T w4y = r[23] * x + r[25] * y + r[26] * z;
+    const T w4z = r[24] * x + r[26] * y + r[27] * z;
+    P3 = x * (v3x + w4x) + y * (v3y + w4y) + z * (v3z + w4z);
+    g3x = T(3) * v3x + (w4x + w4x);
+    g3y = T(3) * v3y + (w4y + w4y);
+    g3z = T(3) * v3z + (w4z + w4z);
+    // order 4: cubic monomials with their multiplicities folded in
+    const T x3 = T(3) * x, y3 = T(3) * y, z3 = T(3) * z;
+    const T cxxx = xx * x, cxxy = xx * y3, cxxz = xx * z3, cxyy = yy * x3, cxyz = qxy * z3;
+    const T cxzz = zz * x3, cyyy = yy * y, cyyz = yy * z3, cyzz = zz * y3, czzz = zz * z;
+    v4x = r[28] * cxxx + r[29] * cxxy + r[30] * cxxz + r[31] * cxyy + r[32] * cxyz +
+          r[33] * cxzz + r[34] * cyyy + r[35] * cyyz + r[36] * cyzz + r[37] * czzz;
+    v4y = r[29] * cxxx + r[31] * cxxy + r[32] * cxxz + r[34] * cxyy + r[35] * cxyz +
+          r[36] * cxzz + r[38] * cyyy + r[39] * cyyz + r[40] * cyzz + r[41] * czzz;
+    v4z = r[30] * cxxx + r[32] * cxxy + r[33] * cxxz + r[35] * cxyy + r[36] * cxyz +
+          r[37] * cxzz + r[39] * cyyy + r[40] * cyyz + r[41] * cyzz + r[42] * czzz;
+    P4 = x * v4x + y * v4y + z * v4z;
+}
+
+struct Acc4 {
+    float x, y, z, p;
+};
+
+__device__ __forceinline__ void pp_one(float sx, float sy, float sz, float m, float px, float py,
+                                       float pz, float eps2, Acc4& A) {
+    // source minus sink: the force on the sink points along +d
+    const float dx = sx - px, dy = sy - py, dz = sz - pz;
+    const float D = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float w = __builtin_amdgcn_rsqf(D);
+    const float mw = m * w;
+    const float w2 = w * w;
+    const float mw3 = mw * w2;
+    A.p -= mw;
+    A.x = fmaf(mw3, dx, A.x);
+    A.y = fmaf(mw3, dy, A.y);
+    A.z = fmaf(mw3, dz, A.z);
+}
+
+__device__ __forceinline__ void pc_one(const float (&r)[kRec], float cx, float cy, float cz,
+                                       float px, float py, float pz, float eps2, Acc4& A) {
+    const float x = px - cx, y = py - cy, z = pz - cz;  // R = sink - centre
+    const float D = fmaf(x, x, fmaf(y, y, fmaf(z, z, eps2)));
+    const float a0 = __builtin_amdgcn_rsqf(D);
+    const float u = -(a0 * a0);
+    const float a1 = a0 * u;
+    const float a2 = a1 * (3.f * u);
+    const float a3 = a2 * (5.f * u);
+    const float a4 = a3 * (7.f * u);
+    const float a5 = a4 * (9.f * u);
+    float P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
+    multipole_terms<float>(r, x, y, z, P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z);
+    A.p -= a0 * r[0] + a1 * r[1] + a2 * P2 + a3 * P3 + a4 * P4;
+    const float S = a1 * r[0] + a2 * r[1] + a3 * P2 + a4 * P3 + a5 * P4;
+    const float a4x4 = 4.f * a4;
+    A.x += S * x + a2 * g2x + a3 * g3x + a4x4 * v4x;
+    A.y += S * y + a2 * g2y + a3 * g3y + a4x4 * v4y;
+    A.z += S * z + a2 * g2z + a3 * g3z + a4x4 * v4z;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Persistent PP + PC kernel.  One wavefront per work item (a sink bucket
+// of up to 16 particles).  The sink particles are wave-uniform (scalar
+// registers); lanes own sources: PP source particles expanded into LDS,
+// PC cells' coefficient records in vector registers.  Each lane keeps
+// 16 x 4 partial sums; a transposing butterfly reduction leaves lane l
+// with component l&3 of sink l>>2.
+__global__ void __launch_bounds__(kWave) k_interact(RunArgs a) {
+    __shared__ float4 lds[kLdsSrc];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(&a.ctl->head, 1);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+        const int n_items = __builtin_amdgcn_readfirstlane(
+            __atomic_load_n(&a.ctl->n_items, __ATOMIC_RELAXED));
+        if (item >= n_items) break;
+        const int b = __builtin_amdgcn_readfirstlane(a.items[item]);
+        const BucketWork* wk = a.work + b;
+        const int first = __builtin_amdgcn_readfirstlane(wk->first);
+        const int nsink = __builtin_amdgcn_readfirstlane(wk->nsink);
+        if (nsink <= 0) continue;
+
+        float sx[kBucket], sy[kBucket], sz[kBucket];
+#pragma unroll
+        for (int i = 0; i < kBucket; ++i) {
+            const int p = first + (i < nsink ? i : nsink - 1);
+            const float4 q = a.pdat[p];
+            sx[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q.x)));
+            sy[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q.y)));
+            sz[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q.z)));
+        }
+        Acc4 acc[kBucket];
+#pragma unroll
+        for (int i = 0; i < kBucket; ++i) acc[i] = Acc4{0.f, 0.f, 0.f, 0.f};
+
+        if (a.parts & MGRAV_PART_PP) {
+            const int64_t e0 = wk->pp0, e1 = wk->pp1;
+            for (int64_t c0 = e0; c0 < e1; c0 += kChunk) {
+                const int64_t e = c0 + lane;
+                int cnt = 0, sfirst = 0;
+                float4 ent = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (e < e1) {
+                    ent = a.ppent[e];
+                    const uint32_t bits = __float_as_uint(ent.w);
+                    sfirst = int(bits & 0x07FFFFFFu);
+                    cnt = int(bits >> 27);
+                }
+                const int incl = wave_incl_scan(cnt, lane);
+                const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
+                const int base = incl - cnt;
+                for (int k = 0; k < cnt; ++k) {
+                    const float4 q = a.pdat[sfirst + k];
+                    lds[base + k] = make_float4(q.x + ent.x, q.y + ent.y, q.z + ent.z, q.w);
+                }
+                __syncthreads();
+                for (int t0 = 0; t0 < total; t0 += kWave) {
+                    const int t = t0 + lane;
+                    // padding lanes: a massless source at the bucket centre (finite, adds 0)
+                    const float4 s = t < total ? lds[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int i = 0; i < kBucket; ++i)
+                        if (i < nsink) pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                }
+                __syncthreads();
+            }
+        }
+        if (a.parts & MGRAV_PART_PC) {
+            const int64_t f0 = wk->pc0, f1 = wk->pc1;
+            for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
+                const int64_t f = c0 + lane;
+                float r[kRec];
+                float cx = 0.f, cy = 0.f, cz = 0.f;  // padding: zero moments at the centre
+                int cell = -1;
+                if (f < f1) {
+                    const float4 ent = a.pcent[f];
+                    cx = ent.x;
+                    cy = ent.y;
+                    cz = ent.z;
+                    cell = __float_as_int(ent.w);
+                }
+                if (cell >= 0) {
+                    const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
+#pragma unroll
+                    for (int i = 0; i < kRec / 4; ++i) {
+                        const float4 q = rec[i];
+                        r[4 * i] = q.x;
+                        r[4 * i + 1] = q.y;
+                        r[4 * i + 2] = q.z;
+                        r[4 * i + 3] = q.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kRec; ++i) r[i] = 0.f;
+                }
+#pragma unroll
+                for (int i = 0; i < kBucket; ++i)
+                    if (i < nsink) pc_one(r, cx, cy, cz, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+            }
+        }
+
+        // transposing butterfly: v[4*i + c] summed over lanes -> lane 4*i + c
+        float v[4 * kBucket];
+#pragma unroll
+        for (int i = 0; i < kBucket; ++i) {
+            v[4 * i] = acc[i].x;
+            v[4 * i + 1] = acc[i].y;
+            v[4 * i + 2] = acc[i].z;
+            v[4 * i + 3] = acc[i].p;
+        }
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) {
+            const bool up = (lane & o) != 0;
+#pragma unroll
+            for (int k = 0; k < o; ++k) {
+                const float keep = up ? v[k + o] : v[k];
+                const float send = up ? v[k] : v[k + o];
+                v[k] = keep + __shfl_xor(send, o);
+            }
+        }
+        const int i = lane >> 2, comp = lane & 3;
+        if (i < nsink) {
+            const int p = first + i;
+            if (a.active == nullptr || a.active[p]) {
+                float val = v[0];
+                if (comp == 3 && (a.parts & MGRAV_PART_PP) && wk->self) {
+                    // remove the self pair, which entered as -m_i / eps
+                    const float4 q = a.pdat[p];
+                    const float D = fmaf(0.f, 0.f, fmaf(0.f, 0.f, fmaf(0.f, 0.f, a.eps2)));
+                    val += q.w * __builtin_amdgcn_rsqf(D);
+                }
+                float* out = comp == 3 ? a.pot : a.acc + int64_t(comp) * a.n;
+                out[p] = val;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// Ewald correction (FP64)
+// ---------------------------------------------------------------------
+struct EwaldArgs {
+    int64_t n;
+    const double* __restrict__ pos;
+    const double* __restrict__ mom;   // root = cell 0
+    const double* __restrict__ com;   // root = cell 0
+    const uint8_t* __restrict__ active;
+    double* table;                    // workspace: [0..43] coefficients, [64..] k-table
+    float* __restrict__ acc;
+    float* __restrict__ pot;
+    double L, alpha;
+    int real_layers, h2max, hmax, order, accumulate;
+};
+
+// Packed symmetric components of orders 2, 3, 4: multiplicity (number of
+// index orderings) and axes.
+__constant__ int c_m2[6] = {1, 2, 2, 1, 2, 1};
+__constant__ int c_ax2[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+__constant__ int c_m3[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
+__constant__ int c_ax3[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
+                                 {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
+__constant__ int c_m4[15] = {1, 4, 4, 6, 12, 6, 4, 12, 12, 4, 1, 4, 6, 4, 1};
+__constant__ int c_ax4[15][4] = {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0, 1, 1},
+                                 {0, 0, 1, 2}, {0, 0, 2, 2}, {0, 1, 1, 1}, {0, 1, 1, 2},
+                                 {0, 1, 2, 2}, {0, 2, 2, 2}, {1, 1, 1, 1}, {1, 1, 1, 2},
+                                 {1, 1, 2, 2}, {1, 2, 2, 2}, {2, 2, 2, 2}};
+
+// Root coefficients in unit-box scaling (order k scaled by L^-k), masked
+// by the requested order, and the k-space table for the half space of
+// wave vectors (each row stands for h and -h).
+__global__ void k_ewald_setup(EwaldArgs a) {
+    if (threadIdx.x != 0) return;
+    const double* m = a.mom;
+    const double L = a.L, L2 = L * L, L3 = L2 * L, L4 = L3 * L;
+    double r[kRec];
+    r[0] = m[0];
+    r[1] = 0.5 * (m[1] + m[4] + m[6]) / L2;
+    for (int i = 0; i < 6; ++i) r[2 + i] = 0.5 * m[1 + i] / L2;
+    r[8] = -0.5 * (m[7] + m[10] + m[12]) / L3;
+    r[9] = -0.5 * (m[8] + m[13] + m[15]) / L3;
+    r[10] = -0.5 * (m[9] + m[14] + m[16]) / L3;
+    r[11] = 0.125 * (m[17] + m[27] + m[31] + 2.0 * (m[20] + m[22] + m[29])) / L4;
+    for (int i = 0; i < 10; ++i) r[12 + i] = -m[7 + i] / 6.0 / L3;
+    r[22] = 0.25 * (m[17] + m[20] + m[22]) / L4;
+    r[23] = 0.25 * (m[18] + m[23] + m[25]) / L4;
+    r[24] = 0.25 * (m[19] + m[24] + m[26]) / L4;
+    r[25] = 0.25 * (m[20] + m[27] + m[29]) / L4;
+    r[26] = 0.25 * (m[21] + m[28] + m[30]) / L4;
+    r[27] = 0.25 * (m[22] + m[29] + m[31]) / L4;
+    for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0 / L4;
+    r[43] = 0.0;
+    if (a.order < 4) {  // drop orders 3 and 4 (and their traces)
+        for (int i = 8; i < 11; ++i) r[i] = 0.0;
+        r[11] = 0.0;
+        for (int i = 12; i < kRec; ++i) r[i] = 0.0;
+    }
+    if (a.order < 2) {
+        for (int i = 1; i < kRec; ++i) r[i] = 0.0;
+    }
+    for (int i = 0; i < kRec; ++i) a.table[i] = r[i];
+
+    // k-space: phi += -(1/pi) sum_h c_h (A_h cos th + B_h sin th), th = 2 pi h.r,
+    // c_h = exp(-pi^2 h^2 / alpha^2) / h^2, A_h = M - 2 pi^2 Q2 + 2 pi^4/3 Q4,
+    // B_h = -4 pi^3/3 Q3, Q_k = M_k[h..h] (unit-box moments).
+    const double PI = 3.14159265358979323846;
+    const int hm = a.hmax;
+    int nk = 0;
+    double* tab = a.table + 64;
+    for (int hx = 0; hx <= hm; ++hx)
+        for (int hy = -hm; hy <= hm; ++hy)
+            for (int hz = -hm; hz <= hm; ++hz) {
+                const int h2 = hx * hx + hy * hy + hz * hz;
+                if (h2 == 0 || h2 > a.h2max) continue;
+                if (hx == 0 && (hy < 0 || (hy == 0 && hz < 0))) continue;  // half space
+                if (nk >= kMaxHalfK) continue;
+                const double h[3] = {double(hx), double(hy), double(hz)};
+                double Q2 = 0, Q3 = 0, Q4 = 0;
+                for (int q = 0; q < 6; ++q) Q2 += c_m2[q] * m[1 + q] / L2 * h[c_ax2[q][0]] * h[c_ax2[q][1]];
+                for (int q = 0; q < 10; ++q)
+                    Q3 += c_m3[q] * m[7 + q] / L3 * h[c_ax3[q][0]] * h[c_ax3[q][1]] * h[c_ax3[q][2]];
+                for (int q = 0; q < 15; ++q)
+                    Q4 += c_m4[q] * m[17 + q] / L4 * h[c_ax4[q][0]] * h[c_ax4[q][1]] *
+                          h[c_ax4[q][2]] * h[c_ax4[q][3]];
+                if (a.order < 4) Q3 = Q4 = 0.0;
+                if (a.order < 2) Q2 = 0.0;
+                const double A = m[0] - 2.0 * PI * PI * Q2 + 2.0 * PI * PI * PI * PI / 3.0 * Q4;
+                const double B = -4.0 * PI * PI * PI / 3.0 * Q3;
+                const double c = exp(-PI * PI * h2 / (a.alpha * a.alpha)) / h2;
+                double* row = tab + 8 * nk;
+                row[0] = h[0];
+                row[1] = h[1];
+                row[2] = h[2];
+                row[3] = -(2.0 / PI) * c * A;  // cos coefficient of phi (pair doubled)
+                row[4] = -(2.0 / PI) * c * B;  // sin coefficient of phi
+                row[5] = -4.0 * c * A;         // sin coefficient of acc / h
+                row[6] = 4.0 * c * B;          // cos coefficient of acc / h
+                row[7] = 0.0;
+                ++nk;
+            }
+    a.table[44] = double(nk);
+    a.table[45] = m[0] * PI / (a.alpha * a.alpha);  // background constant
+}
+
+// Radial derivatives g_n = ((1/r) d/dr)^n of erf(alpha r)/r (near images)
+// or of -erfc(alpha r)/r (outer real-space shells), n = 0..5, unit box.
+// Near images with alpha r < sqrt(2): g_5 from its power series, the rest
+// by the downward recurrence g_n = -(r^2 g_{n+1} + k_{n+1} e^{-alpha^2 r^2})
+// / (2n+1) with k_m = (-2 alpha^2)^m / (alpha sqrt(pi)); otherwise upward
+// from the closed form (the same recurrence solved for g_{n+1}).
+__device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
+    const double SQRT_PI = 1.77245385090551602729;
+    const double al2 = alpha * alpha;
+    const double x = al2 * r2;
+    const double E = exp(-x);
+    double k[6];
+    k[0] = 1.0 / (alpha * SQRT_PI);
+    for (int m = 1; m < 6; ++m) k[m] = k[m - 1] * (-2.0 * al2);
+    if (near) {
+        if (x < 2.0) {
+            double s = 0.0, term = 1.0;
+            for (int j = 0; j < 30; ++j) {
+                s += term / double(2 * j + 11);
+                term *= -x / double(j + 1);
+            }
+            g[5] = 2.0 * alpha / SQRT_PI * (-32.0 * al2 * al2 * al2 * al2 * al2) * s;
+            for (int n = 4; n >= 0; --n) g[n] = -(r2 * g[n + 1] + k[n + 1] * E) / double(2 * n + 1);
+        } else {
+            const double r = sqrt(r2);
+            g[0] = erf(alpha * r) / r;
+            for (int n = 0; n < 5; ++n) g[n + 1] = -(double(2 * n + 1) * g[n] + k[n + 1] * E) / r2;
+        }
+    } else {
+        const double r = sqrt(r2);
+        double e = erfc(alpha * r) / r;
+        g[0] = -e;
+        for (int n = 0; n < 5; ++n) {
+            e = (-double(2 * n + 1) * e + k[n + 1] * E) / r2;
+            g[n + 1] = -e;
+        }
+    }
+}
+
+struct TableRec {
+    const double* t;
+    __device__ double operator[](int i) const { return t[i]; }
+};
+
+__global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.active && !a.active[i]) return;
+    const TableRec rec{a.table};
+    const double invL = 1.0 / a.L;
+    const double rx = (a.pos[3 * i] - a.com[0]) * invL;
+    const double ry = (a.pos[3 * i + 1] - a.com[1]) * invL;
+    const double rz = (a.pos[3 * i + 2] - a.com[2]) * invL;
+    double phi = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+    const int R = a.real_layers;
+    for (int ix = -R; ix <= R; ++ix)
+        for (int iy = -R; iy <= R; ++iy)
+            for (int iz = -R; iz <= R; ++iz) {
+                const bool near = ix >= -1 && ix <= 1 && iy >= -1 && iy <= 1 && iz >= -1 && iz <= 1;
+                const double x = rx - ix, y = ry - iy, z = rz - iz;
+                double g[6];
+                ewald_radial(x * x + y * y + z * z, a.alpha, near, g);
+                double P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
+                multipole_terms<double>(rec, x, y, z, P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z,
+                                        v4x, v4y, v4z);
+                // psi enters with a + sign: phi += sum_n g_n P_n, acc = -grad
+                phi += g[0] * rec[0] + g[1] * rec[1] + g[2] * P2 + g[3] * P3 + g[4] * P4;
+                const double S = g[1] * rec[0] + g[2] * rec[1] + g[3] * P2 + g[4] * P3 + g[5] * P4;
+                const double g44 = 4.0 * g[4];
+                ax -= S * x + g[2] * g2x + g[3] * g3x + g44 * v4x;
+                ay -= S * y + g[2] * g2y + g[3] * g3y + g44 * v4y;
+                az -= S * z + g[2] * g2z + g[3] * g3z + g44 * v4z;
+            }
+    // k space: walk the wave-vector box in the order of the table rows,
+    // advancing e^{i 2 pi h.r} by one rotation per step (no indexed arrays).
+    const int hm = a.hmax;
+    double s1x, c1x, s1y, c1y, s1z, c1z;
+    sincospi(2.0 * rx, &s1x, &c1x);
+    sincospi(2.0 * ry, &s1y, &c1y);
+    sincospi(2.0 * rz, &s1z, &c1z);
+    // e^{-i 2 pi hm y} and e^{-i 2 pi hm z}
+    double cym = 1.0, sym = 0.0, czm = 1.0, szm = 0.0;
+    for (int m = 0; m < hm; ++m) {
+        double t = cym * c1y + sym * s1y;
+        sym = sym * c1y - cym * s1y;
+        cym = t;
+        t = czm * c1z + szm * s1z;
+        szm = szm * c1z - czm * s1z;
+        czm = t;
+    }
+    const double* tab = a.table + 64;
+    const int nk = int(a.table[44]);
+    int q = 0;
+    double cxh = 1.0, sxh = 0.0;  // e^{i 2 pi hx x}
+    for (int hx = 0; hx <= hm; ++hx) {
+        double cyh = cym, syh = sym;  // e^{i 2 pi hy y}, hy from -hm
+        for (int hy = -hm; hy <= hm; ++hy) {
+            const double cxy = cxh * cyh - sxh * syh, sxy = sxh * cyh + cxh * syh;
+            double czh = czm, szh = szm;
+            for (int hz = -hm; hz <= hm; ++hz) {
+                const int h2 = hx * hx + hy * hy + hz * hz;
+                const bool half = hx > 0 || hy > 0 || (hy == 0 && hz > 0);
+                if (h2 > 0 && h2 <= a.h2max && half && q < nk) {
+                    const double* row = tab + 8 * q;
+                    ++q;
+                    const double c = cxy * czh - sxy * szh, s = sxy * czh + cxy * szh;
+                    phi += row[3] * c + row[4] * s;
+                    const double f = row[5] * s + row[6] * c;
+                    ax += f * double(hx);
+                    ay += f * double(hy);
+                    az += f * double(hz);
+                }
+                const double t = czh * c1z - szh * s1z;
+                szh = szh * c1z + czh * s1z;
+                czh = t;
+            }
+            const double t = cyh * c1y - syh * s1y;
+            syh = syh * c1y + cyh * s1y;
+            cyh = t;
+        }
+        const double t = cxh * c1x - sxh * s1x;
+        sxh = sxh * c1x + cxh * s1x;
+        cxh = t;
+    }
+    phi += a.table[45];
+    // physical units: potential / L, acceleration / L^2
+    phi *= invL;
+    const double invL2 = invL * invL;
+    ax *= invL2;
+    ay *= invL2;
+    az *= invL2;
+    float* px = a.acc + i;
+    float* py = a.acc + a.n + i;
+    float* pz = a.acc + 2 * a.n + i;
+    if (a.accumulate) {
+        *px = float(double(*px) + ax);
+        *py = float(double(*py) + ay);
+        *pz = float(double(*pz) + az);
+        a.pot[i] = float(double(a.pot[i]) + phi);
+    } else {
+        *px = float(ax);
+        *py = float(ay);
+        *pz = float(az);
+        a.pot[i] = float(phi);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------
+namespace mgrav_internal {
+thread_local std::string g_host_error;
+mgrav_status set_host_error(mgrav_status s, const std::string& msg) {
+    g_host_error = msg;
+    return s;
+}
+}  // namespace mgrav_internal
+
+struct mgrav_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    int interact_blocks = 0;
+    int occupancy_status = 0;
+    std::string err;
+    bool bound = false;
+    bool failed = false;
+    mgrav_problem prob{};
+    char* ws = nullptr;
+    Layout lay{};
+    mgrav_ewald ewald{};
+    const uint8_t* active = nullptr;
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_e1 = nullptr;  // around k_interact / k_ewald
+    bool have_run = false;
+    // graph cache: the captured launch sequence and the arguments it holds
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    struct LaunchSet* g_set = nullptr;
+    bool no_graph = false;        // capture failed once: launch directly
+    Control* host_ctl = nullptr;  // pinned
+};
+
+// Everything a compute launches, compared byte-wise to decide whether the
+// captured graph can be replayed.
+struct LaunchSet {
+    RunArgs r;
+    EwaldArgs e;
+    int64_t n, n_bucket;
+    int use_mask, tree, ewald, interact_blocks;
+};
+
+namespace {
+
+mgrav_status fail(mgrav_ctx* c, mgrav_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    mgrav_internal::g_host_error = msg;
+    return s;
+}
+
+mgrav_status hip_fail(mgrav_ctx* c, hipError_t e, const char* what) {
+    return fail(c, MGRAV_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+void drop_graph(mgrav_ctx* c) {
+    for (int i = 0; i < 3; ++i) {
+        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+        c->gexec[i] = nullptr;
+        c->graph[i] = nullptr;
+    }
+    delete c->g_set;
+    c->g_set = nullptr;
+}
+
+StageArgs stage_args(mgrav_ctx* c) {
+    const mgrav_problem& p = c->prob;
+    StageArgs a{};
+    a.n = p.n;
+    a.n_cell = p.n_cell;
+    a.n_bucket = p.n_bucket;
+    a.n_pp = p.n_pp;
+    a.n_pc = p.n_pc;
+    a.n_images = p.n_images;
+    a.L = p.box_L;
+    a.pos = p.pos;
+    a.mass = p.mass;
+    a.cell_first = p.cell_first;
+    a.cell_count = p.cell_count;
+    a.child = p.child;
+    a.com = p.com;
+    a.bbox = p.bbox;
+    a.mom = p.mom;
+    a.bucket_cell = p.bucket_cell;
+    a.pp_off = p.pp_off;
+    a.pp_src = p.pp_src;
+    a.pp_img = p.pp_img;
+    a.pc_off = p.pc_off;
+    a.pc_src = p.pc_src;
+    a.pc_img = p.pc_img;
+    char* w = c->ws;
+    a.ctl = reinterpret_cast<Control*>(w + c->lay.ctl);
+    a.pdat = reinterpret_cast<float4*>(w + c->lay.pdat);
+    a.work = reinterpret_cast<BucketWork*>(w + c->lay.work);
+    a.cellrec = reinterpret_cast<float*>(w + c->lay.cellrec);
+    a.ppent = reinterpret_cast<float4*>(w + c->lay.ppent);
+    a.pcent = reinterpret_cast<float4*>(w + c->lay.pcent);
+    return a;
+}
+
+mgrav_status check_problem(mgrav_ctx* c, const mgrav_problem* p) {
+    if (!p) return fail(c, MGRAV_ERR_INVALID_ARG, "problem is NULL");
+    if (p->n < 1 || p->n > MGRAV_MAX_PARTICLES)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "n must be in 1 .. 2^27");
+    if (p->n_cell < 1 || p->n_bucket < 1 || p->n_bucket > p->n || p->n_cell > 2 * p->n)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "bad n_cell / n_bucket");
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "eps must be finite and > 0");
+    if (!(p->theta > 0.0)) return fail(c, MGRAV_ERR_INVALID_ARG, "theta must be > 0");
+    if (p->n_images != 1 && p->n_images != 27)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "n_images must be 1 or 27");
+    if (p->n_images == 27 && !(p->box_L > 0.0))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "27 images need box_L > 0");
+    if (p->box_L < 0.0 || !std::isfinite(p->box_L))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "bad box_L");
+    if (p->n_pp < 0 || p->n_pc < 0) return fail(c, MGRAV_ERR_INVALID_ARG, "negative list size");
+    if (!p->pos || !p->mass || !p->cell_first || !p->cell_count || !p->child || !p->com ||
+        !p->bbox || !p->mom || !p->bucket_cell || !p->pp_off || !p->pc_off)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "null device pointer in problem");
+    if ((p->n_pp > 0 && (!p->pp_src || !p->pp_img)) || (p->n_pc > 0 && (!p->pc_src || !p->pc_img)))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "null list pointer");
+    return MGRAV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgrav_version(void) { return MGRAV_VERSION_MAJOR * 1000 + MGRAV_VERSION_MINOR; }
+
+const char* mgrav_status_string(mgrav_status s) {
+    switch (s) {
+    case MGRAV_OK: return "ok";
+    case MGRAV_ERR_INVALID_ARG: return "invalid argument";
+    case MGRAV_ERR_BAD_TREE: return "bad tree";
+    case MGRAV_ERR_BAD_LIST: return "bad interaction list";
+    case MGRAV_ERR_DEVICE: return "device error";
+    case MGRAV_ERR_NO_MEMORY: return "workspace too small";
+    case MGRAV_ERR_TIMEOUT: return "timeout";
+    case MGRAV_ERR_STATE: return "call out of order";
+    case MGRAV_ERR_NOT_TRAINED: return "surrogate not trained";
+    }
+    return "unknown status";
+}
+
+const char* mgrav_last_error(const mgrav_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : mgrav_internal::g_host_error.c_str();
+}
+
+mgrav_status mgrav_create(int device, void* hip_stream, mgrav_ctx** out) {
+    if (!out) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "no such device");
+    mgrav_ctx* c = new mgrav_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(nullptr, e, "hipSetDevice");
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(nullptr, e, "hipGetDeviceProperties");
+    }
+    c->n_cu = prop.multiProcessorCount;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_interact, kWave, 0);
+    if (e != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();  // tolerated: fall back to a fixed occupancy
+        per_cu = 8;
+    }
+    c->occupancy_status = int(e);
+    c->interact_blocks = per_cu * c->n_cu;
+    if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_end) != hipSuccess ||
+        hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
+        hipEventCreate(&c->ev_e1) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->host_ctl), sizeof(Control)) != hipSuccess) {
+        mgrav_destroy(c);
+        return fail(nullptr, MGRAV_ERR_DEVICE, "event / pinned allocation failed");
+    }
+    *out = c;
+    return MGRAV_OK;
+}
+
+void mgrav_destroy(mgrav_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+    if (c->ev_end) (void)hipEventDestroy(c->ev_end);
+    if (c->ev_k0) (void)hipEventDestroy(c->ev_k0);
+    if (c->ev_k1) (void)hipEventDestroy(c->ev_k1);
+    if (c->ev_e1) (void)hipEventDestroy(c->ev_e1);
+    if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    delete c;
+}
+
+mgrav_status mgrav_workspace_size(const mgrav_problem* p, size_t* bytes) {
+    if (!bytes) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "bytes is NULL");
+    mgrav_status s = check_problem(nullptr, p);
+    if (s != MGRAV_OK) return s;
+    *bytes = make_layout(p->n, p->n_cell, p->n_bucket, p->n_pp, p->n_pc).total;
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_bind(mgrav_ctx* c, const mgrav_problem* p, void* workspace, size_t bytes) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    mgrav_status s = check_problem(c, p);
+    if (s != MGRAV_OK) return s;
+    const Layout lay = make_layout(p->n, p->n_cell, p->n_bucket, p->n_pp, p->n_pc);
+    if (!workspace) return fail(c, MGRAV_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < lay.total) return fail(c, MGRAV_ERR_NO_MEMORY, "workspace too small");
+    HIP_TRY(c, hipSetDevice(c->device));
+    c->prob = *p;
+    c->ws = static_cast<char*>(workspace);
+    c->lay = lay;
+    c->bound = false;
+    c->failed = false;
+    c->have_run = false;
+    c->active = nullptr;
+    if (p->box_L > 0.0 && p->n_images == 27)
+        c->ewald = mgrav_ewald{MGRAV_EWALD_EXACT, 2.6, 1, 10, 4, 1};
+    else
+        c->ewald = mgrav_ewald{MGRAV_EWALD_NONE, 2.6, 1, 10, 4, 1};
+
+    const StageArgs a = stage_args(c);
+    hipLaunchKernelGGL(k_init_control, dim3(1), dim3(kWave), 0, c->stream, a.ctl);
+    const int64_t nt = p->n_bucket * kBucket;
+    hipLaunchKernelGGL(k_stage_particles, dim3(unsigned((nt + 255) / 256)), dim3(256), 0,
+                       c->stream, a);
+    hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((p->n_cell + 255) / 256)), dim3(256), 0,
+                       c->stream, a);
+    hipLaunchKernelGGL(k_stage_pp, dim3(unsigned(p->n_bucket)), dim3(kWave), 0, c->stream, a);
+    hipLaunchKernelGGL(k_stage_pc, dim3(unsigned(p->n_bucket)), dim3(kWave), 0, c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+    c->bound = true;
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_set_ewald(mgrav_ctx* c, const mgrav_ewald* cfg) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (!c->bound) return fail(c, MGRAV_ERR_STATE, "set_ewald before bind");
+    if (!cfg) return fail(c, MGRAV_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->mode == MGRAV_EWALD_NONE) {
+        c->ewald = *cfg;
+        return MGRAV_OK;
+    }
+    if (cfg->mode == MGRAV_EWALD_SURROGATE)
+        return fail(c, MGRAV_ERR_NOT_TRAINED, "no surrogate weights loaded");
+    if (cfg->mode != MGRAV_EWALD_EXACT) return fail(c, MGRAV_ERR_INVALID_ARG, "unknown mode");
+    if (!(c->prob.box_L > 0.0) || c->prob.n_images != 27)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "Ewald needs a periodic problem");
+    if (!(cfg->alpha > 0.5 && cfg->alpha < 10.0))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "alpha outside (0.5, 10)");
+    if (cfg->real_layers < 1 || cfg->real_layers > 4)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "real_layers outside 1..4");
+    if (cfg->h2max < 0 || cfg->h2max > kMaxH2)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "h2max outside 0..64");
+    if (cfg->order != 0 && cfg->order != 2 && cfg->order != 4)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "order must be 0, 2 or 4");
+    c->ewald = *cfg;
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_set_active(mgrav_ctx* c, const uint8_t* active_dev) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (!c->bound) return fail(c, MGRAV_ERR_STATE, "set_active before bind");
+    c->active = active_dev;
+    return MGRAV_OK;
+}
+
+static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchSet* L) {
+    std::memset(L, 0, sizeof(*L));  // padding too: the struct is compared byte-wise
+    const mgrav_problem& p = c->prob;
+    char* w = c->ws;
+    RunArgs& r = L->r;
+    r.n = p.n;
+    r.n_bucket = p.n_bucket;
+    r.active = c->active;
+    r.ctl = reinterpret_cast<Control*>(w + c->lay.ctl);
+    r.pdat = reinterpret_cast<const float4*>(w + c->lay.pdat);
+    r.work = reinterpret_cast<const BucketWork*>(w + c->lay.work);
+    r.items = reinterpret_cast<int*>(w + c->lay.items);
+    r.cellrec = reinterpret_cast<const float*>(w + c->lay.cellrec);
+    r.ppent = reinterpret_cast<const float4*>(w + c->lay.ppent);
+    r.pcent = reinterpret_cast<const float4*>(w + c->lay.pcent);
+    r.acc = acc;
+    r.pot = pot;
+    r.eps2 = float(p.eps * p.eps);
+    r.parts = parts;
+    L->n = p.n;
+    L->n_bucket = p.n_bucket;
+    L->use_mask = c->active ? 1 : 0;
+    L->tree = (parts & (MGRAV_PART_PP | MGRAV_PART_PC)) != 0;
+    L->ewald = (parts & MGRAV_PART_EWALD) && c->ewald.mode == MGRAV_EWALD_EXACT;
+    L->interact_blocks =
+        int(p.n_bucket < c->interact_blocks ? p.n_bucket : c->interact_blocks);
+    if (L->ewald) {
+        EwaldArgs& e = L->e;
+        e.n = p.n;
+        e.pos = p.pos;
+        e.mom = p.mom;
+        e.com = p.com;
+        e.active = c->active;
+        e.table = reinterpret_cast<double*>(w + c->lay.ewald);
+        e.acc = acc;
+        e.pot = pot;
+        e.L = p.box_L;
+        e.alpha = c->ewald.alpha;
+        e.real_layers = c->ewald.real_layers;
+        e.h2max = c->ewald.h2max;
+        e.hmax = int(std::floor(std::sqrt(double(e.h2max)) + 1e-9));
+        e.order = c->ewald.order;
+        e.accumulate = L->tree;
+    }
+}
+
+// The launch sequence in three phases: 0 = queue set-up, 1 = PP + PC,
+// 2 = Ewald.  Each phase is captured as its own graph so that timing
+// events can be recorded between them on the stream.
+static bool phase_used(const LaunchSet& L, int phase) {
+    return phase == 0 || (phase == 1 && L.tree) || (phase == 2 && L.ewald);
+}
+
+static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
+    if (phase == 0) {
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
+                           int(L.n_bucket), L.use_mask);
+        hipLaunchKernelGGL(k_select, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256), 0,
+                           c->stream, L.r);
+    } else if (phase == 1 && L.tree) {
+        hipLaunchKernelGGL(k_interact, dim3(unsigned(L.interact_blocks)), dim3(kWave), 0,
+                           c->stream, L.r);
+    } else if (phase == 2 && L.ewald) {
+        hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kWave), 0, c->stream, L.e);
+        hipLaunchKernelGGL(k_ewald, dim3(unsigned((L.n + 127) / 128)), dim3(128), 0, c->stream,
+                           L.e);
+    }
+}
+
+// Capture the three phases; on any capture failure fall back to direct
+// launches for this context.
+static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
+    hipStreamCaptureStatus cs;
+    if (c->no_graph || c->stream == nullptr ||
+        hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        c->no_graph = true;
+        return;
+    }
+    for (int ph = 0; ph < 3; ++ph) {
+        if (!phase_used(L, ph)) continue;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            enqueue_phase(c, L, ph);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(c->stream, &g);
+            if (e == hipSuccess && g) {
+                c->graph[ph] = g;
+                e = hipGraphInstantiate(&c->gexec[ph], g, nullptr, nullptr, 0);
+            }
+        }
+        if (e != hipSuccess || !c->gexec[ph]) {
+            (void)hipGetLastError();
+            drop_graph(c);
+            c->no_graph = true;
+            return;
+        }
+    }
+    c->g_set = new LaunchSet(L);
+}
+
+mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (!c->bound) return fail(c, MGRAV_ERR_STATE, "compute before bind");
+    if (c->failed) return fail(c, MGRAV_ERR_STATE, "context failed; bind again");
+    if (!acc || !pot) return fail(c, MGRAV_ERR_INVALID_ARG, "null output");
+    if (parts <= 0 || parts > MGRAV_PART_ALL) return fail(c, MGRAV_ERR_INVALID_ARG, "bad parts");
+    HIP_TRY(c, hipSetDevice(c->device));
+    LaunchSet L;
+    make_launch(c, parts, acc, pot, &L);
+    const bool same = c->g_set && std::memcmp(c->g_set, &L, sizeof(L)) == 0;
+    if (!same) {
+        drop_graph(c);
+        capture_graphs(c, L);
+    }
+    hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
+    HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+    for (int ph = 0; ph < 3; ++ph) {
+        if (c->gexec[ph]) {
+            HIP_TRY(c, hipGraphLaunch(c->gexec[ph], c->stream));
+        } else {
+            enqueue_phase(c, L, ph);
+            HIP_TRY(c, hipGetLastError());
+        }
+        HIP_TRY(c, hipEventRecord(marks[ph], c->stream));
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
+    c->have_run = true;
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_compute(mgrav_ctx* c, float* acc, float* pot) {
+    return mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
+}
+
+mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (!c->bound) return fail(c, MGRAV_ERR_STATE, "wait before bind");
+    HIP_TRY(c, hipSetDevice(c->device));
+    // Watchdog: a marker event after all enqueued work, polled until done.
+    hipEvent_t marker;
+    HIP_TRY(c, hipEventCreateWithFlags(&marker, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(marker, c->stream);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(marker);
+        return hip_fail(c, e, "hipEventRecord");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        e = hipEventQuery(marker);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) {
+            (void)hipEventDestroy(marker);
+            return hip_fail(c, e, "device work failed");
+        }
+        const double dt =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (timeout_s > 0.0 && dt > timeout_s) {
+            c->failed = true;
+            return fail(c, MGRAV_ERR_TIMEOUT, "device work did not finish before the deadline");
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.01 ? 20 : 500));
+    }
+    (void)hipEventDestroy(marker);
+    const Control* dctl = reinterpret_cast<const Control*>(c->ws + c->lay.ctl);
+    HIP_TRY(c, hipMemcpy(c->host_ctl, dctl, sizeof(Control), hipMemcpyDeviceToHost));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        if (c->have_run) {
+            stats->n_pp_interactions = int64_t(c->host_ctl->n_pp_int);
+            stats->n_pc_interactions = int64_t(c->host_ctl->n_pc_int);
+            stats->n_active_particles = int64_t(c->host_ctl->n_active_p);
+            stats->n_active_buckets = int64_t(c->host_ctl->n_active_b);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev_start, c->ev_end) == hipSuccess)
+                stats->ms_total = ms;
+            if (hipEventElapsedTime(&ms, c->ev_k0, c->ev_k1) == hipSuccess)
+                stats->ms_interact = ms;
+            if (hipEventElapsedTime(&ms, c->ev_k1, c->ev_e1) == hipSuccess)
+                stats->ms_ewald = ms;
+            stats->graph_replay = c->gexec[0] != nullptr ? 1 : 0;
+        }
+    }
+    const int err = c->host_ctl->err;
+    if (err & kErrTree) return fail(c, MGRAV_ERR_BAD_TREE, "tree check failed on the device");
+    if (err & kErrList) return fail(c, MGRAV_ERR_BAD_LIST, "list check failed on the device");
+    if (err & kErrParticle)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "non-finite position or non-positive mass");
+    return MGRAV_OK;
+}
+
+}  // extern "C"

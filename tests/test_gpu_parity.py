@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same tree and
+lists.  Tolerance: rms relative acceleration error <= 1e-4 (float
+interactions and float accumulation against double everywhere).
+
+Every test prints its case before the first device call."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+try:  # imported at collection so its one-off start-up cost is not a test's
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+TOL_ACC = 1e-4     # rms relative acceleration error, whole path
+TOL_PART = 2e-5    # global relative error of a single part (PP or PC alone)
+TOL_POT = 1e-5     # potential error relative to the rms of the PP + PC potential
+# (in a periodic box the total potential has zero mean, so its own size is
+# no scale for the error; the tree part, which it cancels, is)
+TOL_EWALD = 1e-6   # Ewald correction alone (double, rounded to float once)
+
+
+def _case(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mg_ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1609_08621_amd as mg
+    ctx = mg.Context(0)
+    yield mg, ctx
+    ctx.close()
+
+
+def rel_rms(a, ref):
+    return float(np.sqrt(np.mean(np.sum((a - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
+
+
+def glob_rel(a, ref):
+    return float(np.sqrt(np.sum((a - ref) ** 2) / np.sum(ref ** 2)))
+
+
+def prepared(ps, theta=0.7):
+    tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lists = oracle.build_lists(tree, theta, ps.eps)
+    return tree, lists, ps.pos[tree.perm], ps.mass[tree.perm]
+
+
+def gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts=7, theta=0.7, ewald=None, active=None):
+    mg, ctx = mg_ctx
+    return mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, theta, parts, ewald, active)
+
+
+def check_parts(mg_ctx, ps, label, sample=None):
+    tree, lists, pos_t, mass_t = prepared(ps)
+    mg = mg_ctx[0]
+    res = {}
+    parts_list = [(mg.PART_PP, "PP"), (mg.PART_PC, "PC"), (mg.PART_ALL, "ALL")]
+    if ps.box_L > 0:
+        parts_list.insert(2, (mg.PART_EWALD, "EWALD"))
+    sel = None
+    if sample is not None:
+        sel = np.arange(0, tree.n_bucket, sample, dtype=np.int32)
+    pot_scale = {}
+    for parts, name in parts_list:
+        _case(f"{label} n={ps.n} parts={name} sample={sample}")
+        ag, pg, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts)
+        ao, po = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, parts, buckets=sel)
+        if sel is not None:
+            idx = np.concatenate([np.arange(tree.cell_first[c], tree.cell_first[c] + tree.cell_count[c])
+                                  for c in tree.bucket_cell[sel]])
+            ag, pg, ao, po = ag[idx], pg[idx], ao[idx], po[idx]
+        assert np.all(np.isfinite(ag)) and np.all(np.isfinite(pg))
+        pot_scale[name] = po
+        if name == "ALL":
+            ref = pot_scale["PP"] + pot_scale["PC"]
+            perr = float(np.sqrt(np.sum((pg - po) ** 2) / np.sum(ref ** 2)))
+        else:
+            perr = glob_rel(pg[:, None], po[:, None])
+        res[name] = (rel_rms(ag, ao), glob_rel(ag, ao), perr)
+        print(f"  {name}: rel_rms={res[name][0]:.3e} glob={res[name][1]:.3e} "
+              f"pot={res[name][2]:.3e}  pp={st.n_pp_interactions} pc={st.n_pc_interactions}",
+              flush=True)
+    assert res["PP"][1] < TOL_PART and res["PC"][1] < TOL_PART
+    if "EWALD" in res:
+        assert res["EWALD"][1] < TOL_EWALD and res["EWALD"][2] < TOL_EWALD
+    assert res["ALL"][0] < TOL_ACC, res["ALL"]
+    assert res["ALL"][2] < TOL_POT, res["ALL"]
+    return res
+
+
+def test_plummer_open_full(mg_ctx):
+    check_parts(mg_ctx, workloads.plummer(8192), "plummer_8192")
+
+
+def test_lattice_periodic_small(mg_ctx):
+    check_parts(mg_ctx, workloads.perturbed_lattice(16, 0.2, seed=31), "lattice_16")
+
+
+def test_clustered_periodic_small(mg_ctx):
+    check_parts(mg_ctx, workloads.make(3, scale_n1d=24), "clustered_24")
+
+
+def test_lattice_periodic_full_size_sampled(mg_ctx):
+    check_parts(mg_ctx, workloads.make(2), "lattice_64_full", sample=97)
+
+
+def test_unperturbed_lattice_cancellation(mg_ctx):
+    # The exact force vanishes on the sigma = 0 lattice; what is left is the
+    # method's error.  The GPU must reproduce the oracle's residual field.
+    ps = workloads.perturbed_lattice(16, 0.0)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    _case("lattice_16 sigma=0 ALL")
+    ag, pg, _ = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t)
+    ao, po = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, 7)
+    scale = np.sqrt(np.mean(np.sum(ao ** 2, 1)))
+    err = np.sqrt(np.mean(np.sum((ag - ao) ** 2, 1)))
+    print(f"  residual rms={scale:.3e} gpu-oracle rms={err:.3e}", flush=True)
+    assert err < 2e-3 * scale + 1e-6
+
+
+def test_repeat_is_bitwise_deterministic(mg_ctx):
+    mg, ctx = mg_ctx
+    import torch
+    ps = workloads.make(3, scale_n1d=20)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    _case("clustered_20 repeat x3 through one bound problem (graph replay)")
+    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    outs = []
+    for _ in range(3):
+        acc, pot = ctx.outputs()
+        ctx.compute(acc, pot)
+        ctx.wait(60)
+        outs.append((acc.cpu().numpy(), pot.cpu().numpy()))
+    for a, p_ in outs[1:]:
+        assert np.array_equal(a, outs[0][0]) and np.array_equal(p_, outs[0][1])
+
+
+def test_active_subset_matches_full_run(mg_ctx):
+    mg, ctx = mg_ctx
+    import torch
+    ps = workloads.make(3, scale_n1d=20)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    _case("clustered_20 full then 10% active")
+    ag, pg, st_full = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t)
+    active = workloads.active_by_acceleration(np.linalg.norm(ag, axis=1), 0.1)
+    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    dev = torch.device("cuda", 0)
+    ctx.set_active(torch.from_numpy(active).to(dev))
+    acc = torch.full((3 * ps.n,), 7.0, dtype=torch.float32, device=dev)
+    pot = torch.full((ps.n,), 7.0, dtype=torch.float32, device=dev)
+    ctx.compute(acc, pot)
+    st = ctx.wait(60)
+    a = acc.cpu().numpy().reshape(3, -1).T
+    p_ = pot.cpu().numpy()
+    on = active.astype(bool)
+    assert np.array_equal(a[on], ag[on]) and np.array_equal(p_[on], pg[on])
+    assert np.all(a[~on] == 7.0) and np.all(p_[~on] == 7.0)
+    assert st.n_active_particles == on.sum()
+    assert st.n_pp_interactions < st_full.n_pp_interactions
+
+
+def test_edge_cases(mg_ctx):
+    rng = np.random.default_rng(41)
+    cases = {
+        "single_particle": (rng.uniform(0, 1, (1, 3)), 0.0),
+        "one_bucket_16": (rng.uniform(0, 1, (16, 3)), 0.0),
+        "two_buckets_17": (rng.uniform(0, 1, (17, 3)), 0.0),
+        "coincident_pairs": (np.repeat(rng.uniform(0, 1, (40, 3)), 2, axis=0), 0.0),
+        "periodic_small": (rng.uniform(0, 1, (50, 3)), 1.0),
+    }
+    for name, (pos, L) in cases.items():
+        ps = workloads.ParticleSet(pos, np.full(pos.shape[0], 1.0 / pos.shape[0]), 0.01, L)
+        tree, lists, pos_t, mass_t = prepared(ps)
+        _case(f"edge {name} n={ps.n}")
+        ag, pg, _ = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t)
+        ao, po = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, 7)
+        assert np.all(np.isfinite(ag)) and np.all(np.isfinite(pg))
+        assert np.abs(ag - ao).max() <= 1e-5 * (1 + np.abs(ao).max()), name
+        assert np.abs(pg - po).max() <= 1e-5 * (1 + np.abs(po).max()), name
+
+
+def test_bad_list_entry_is_reported_not_dereferenced(mg_ctx):
+    mg, ctx = mg_ctx
+    ps = workloads.plummer(2000, seed=5)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    bad = oracle.Lists(lists.pp_off, lists.pp_src.copy(), lists.pp_img, lists.pc_off,
+                       lists.pc_src.copy(), lists.pc_img, lists.n_images)
+    bad.pp_src[3] = 10 ** 8        # out of range
+    bad.pc_src[5] = -7             # out of range
+    _case("bad list entries -> BAD_LIST")
+    with pytest.raises(mg.MgravError) as e:
+        gpu(mg_ctx, ps, tree, bad, pos_t, mass_t)
+    assert e.value.status == mg.ERR_BAD_LIST

@@ -1,0 +1,112 @@
+"""CPU tests of the library boundary: symbols, host-side tree/list builders
+against the oracle (integer and index results bit-exact), argument checks.
+No device compute is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+mg = pytest.importorskip("paper_1609_08621_amd")
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mgrav.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgrav_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(mg.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(mg.EXPORTS)
+    assert mg.version() == 1
+
+
+def test_status_strings():
+    for s in range(9):
+        assert mg._lib.mgrav_status_string(s).decode()
+    assert mg._lib.mgrav_status_string(99).decode() == "unknown status"
+
+
+@pytest.fixture(scope="module")
+def sets():
+    return [workloads.plummer(3000, seed=21), workloads.perturbed_lattice(12, 0.2, seed=22),
+            workloads.make(3, scale_n1d=16), workloads.perturbed_lattice(8, 0.0)]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_host_tree_and_lists_equal_oracle(sets, k):
+    ps = sets[k]
+    to = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    tg = mg.tree_build(ps.pos, ps.mass, ps.box_L, 16)
+    for f in ("perm", "cell_first", "cell_count", "child", "bucket_cell"):
+        assert np.array_equal(getattr(to, f), getattr(tg, f)), f
+    # the quantities that decide list membership are computed identically
+    for f in ("com", "bmax", "bbox"):
+        assert np.array_equal(getattr(to, f), getattr(tg, f)), f
+    assert np.allclose(to.mom, tg.mom, rtol=1e-13, atol=1e-300)
+    lo = oracle.build_lists(to, 0.7, ps.eps)
+    lg = mg.lists_build(tg, 0.7, ps.eps)
+    for f in ("pp_off", "pp_src", "pp_img", "pc_off", "pc_src", "pc_img"):
+        assert np.array_equal(getattr(lo, f), getattr(lg, f)), f
+
+
+def test_host_tree_rejects_bad_input():
+    ps = workloads.perturbed_lattice(4, 0.1)
+    with pytest.raises(mg.MgravError) as e:
+        mg.tree_build(ps.pos, ps.mass, ps.box_L, 17)
+    assert e.value.status == mg.ERR_INVALID_ARG
+    bad = ps.pos.copy()
+    bad[3, 1] = 1.5  # outside the periodic box
+    with pytest.raises(mg.MgravError):
+        mg.tree_build(bad, ps.mass, ps.box_L, 16)
+    bad = ps.pos.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(mg.MgravError):
+        mg.tree_build(bad, ps.mass, 0.0, 16)
+    with pytest.raises(mg.MgravError):
+        mg.tree_build(ps.pos, -ps.mass, ps.box_L, 16)
+    t = mg.tree_build(ps.pos, ps.mass, ps.box_L, 16)
+    with pytest.raises(mg.MgravError):
+        mg.lists_build(t, 0.0, ps.eps)
+    with pytest.raises(mg.MgravError):
+        mg.lists_build(t, 0.7, ps.eps, n_images=5)
+
+
+def test_workspace_size_validates_problem():
+    p = mg.Problem()
+    sz = ctypes.c_size_t(0)
+    assert mg._lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == mg.ERR_INVALID_ARG
+    assert b"n must be" in mg._lib.mgrav_last_error(None)
+    # a plausible problem with fake (never dereferenced) device pointers
+    p.n, p.eps, p.theta, p.box_L, p.n_images = 1000, 0.01, 0.7, 0.0, 1
+    p.n_cell, p.n_bucket, p.n_pp, p.n_pc = 127, 64, 500, 900
+    for f in ("pos", "mass", "cell_first", "cell_count", "child", "com", "bbox", "mom",
+              "bucket_cell", "pp_off", "pp_src", "pp_img", "pc_off", "pc_src", "pc_img"):
+        setattr(p, f, 4096)
+    assert mg._lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == mg.OK
+    assert sz.value >= 1000 * 16 + 127 * 176 + 1400 * 16
+    p.eps = 0.0
+    assert mg._lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == mg.ERR_INVALID_ARG
+    p.eps, p.n_images = 0.01, 27  # periodic images without a box
+    assert mg._lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == mg.ERR_INVALID_ARG
+
+
+def test_calls_on_null_context_fail_cleanly():
+    assert mg._lib.mgrav_bind(None, None, None, 0) == mg.ERR_INVALID_ARG
+    assert mg._lib.mgrav_compute(None, None, None) == mg.ERR_INVALID_ARG
+    assert mg._lib.mgrav_wait(None, 1.0, None) == mg.ERR_INVALID_ARG
+    assert mg._lib.mgrav_set_active(None, None) == mg.ERR_INVALID_ARG
+    out = ctypes.c_void_p()
+    assert mg._lib.mgrav_create(0, None, None) == mg.ERR_INVALID_ARG
+    mg._lib.mgrav_destroy(None)
