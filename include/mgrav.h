@@ -213,8 +213,11 @@ mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace,
  * with k in {0} (order 0), {0, 2} (order 2) or {0, 2, 3, 4} (order 4;
  * the paper's "5th order": kernel derivatives through order 5 in the
  * force).  mode NONE switches the correction off (open boundaries need
- * nothing); EXACT uses the sums above.  SURROGATE uses a trained network
- * (mgrav_mlp_*) for psi; SURROGATE without weights fails NOT_TRAINED. */
+ * nothing); EXACT uses the sums above.  SURROGATE evaluates the trained
+ * network of mgrav_mlp_* instead: the field of the monopoles of the
+ * `top_cells` (1 = root, 8 or 64) tree cells at depth log2(top_cells),
+ * psi from the network at every (particle, cell) pair, added in double.
+ * SURROGATE without weights fails NOT_TRAINED. */
 typedef enum {
     MGRAV_EWALD_NONE = 0,
     MGRAV_EWALD_EXACT = 1,
@@ -279,6 +282,68 @@ typedef struct {
  * validation failures from the last bind (BAD_TREE / BAD_LIST).  stats
  * may be NULL. */
 mgrav_status mgrav_wait(mgrav_ctx *ctx, double timeout_s, mgrav_stats *stats);
+
+/* ------------------------------------------------------------------ */
+/* Learned Ewald correction (not in the paper; replaces the exact sums  */
+/* of mgrav_set_ewald's EXACT mode when mode SURROGATE is selected).    */
+/* ------------------------------------------------------------------ */
+
+/* psi and grad psi of a unit mass in the unit box (the kernel described
+ * at mgrav_set_ewald, double precision, the same sums as EXACT mode) at
+ * n points r[n][3] (device); out[n][4] (device) = psi, d psi/dx, d psi/dy,
+ * d psi/dz.  Used to produce training data and as the exact reference.
+ * Errors: INVALID_ARG for alpha outside (0.5, 10), real_layers outside
+ * 1..4, h2max outside 0..64. */
+mgrav_status mgrav_ewald_psi(mgrav_ctx *ctx, const double *r, int64_t n, double alpha,
+                             int real_layers, int h2max, double *out);
+
+/* The surrogate is a network u -> (psi(u) - psi(0) + (2 pi/3)|u|^2,
+ * grad psi(u) + (4 pi/3) u) on the fundamental octant u in [0, 1)^3 of
+ * the unit box (psi is even in every coordinate), 3 -> 128 -> 128 -> 128
+ * -> 4 with SiLU, weights rounded to bfloat16, float accumulation.  Its
+ * parameters are one float vector of 34052 values in the order W1[128][3],
+ * b1[128], W2[128][128], b2[128], W3[128][128], b3[128], W4[4][128], b4[4]
+ * (row-major, output x input).  The network needs a device workspace of
+ * mgrav_mlp_workspace_size(max_batch) bytes (max_batch: largest training
+ * batch, a multiple of 1024), attached to a context; it is borrowed until
+ * the next attach or destroy. */
+mgrav_status mgrav_mlp_workspace_size(int64_t max_batch, size_t *bytes);
+mgrav_status mgrav_mlp_attach(mgrav_ctx *ctx, void *workspace, size_t bytes, int64_t max_batch);
+
+/* Load parameters (host, 34052 floats) and psi(0) of the Ewald parameters
+ * the network was trained for; resets the optimiser state.  Blocking. */
+mgrav_status mgrav_mlp_set_weights(mgrav_ctx *ctx, const float *params, int64_t count,
+                                   double psi0);
+/* Copy the current parameters to the host.  Blocking. */
+mgrav_status mgrav_mlp_get_weights(mgrav_ctx *ctx, float *params, int64_t count);
+
+/* y[n][4] = network(x[n][3]) (device, float).  Asynchronous. */
+mgrav_status mgrav_mlp_forward(mgrav_ctx *ctx, const float *x, int64_t n, float *y);
+
+/* grad[34052] (device) = d(sum_ij dy[i][j] y[i][j]) / d params for
+ * y = network(x), x[n][3], dy[n][4] (device); n a multiple of 1024 and at
+ * most max_batch.  Asynchronous. */
+mgrav_status mgrav_mlp_backward(mgrav_ctx *ctx, const float *x, const float *dy, int64_t n,
+                                float *grad);
+
+typedef struct {
+    int epochs;          /* passes over the samples (1..4096)              */
+    int batch;           /* samples per step, multiple of 1024             */
+    float lr, lr_min;    /* cosine schedule from lr to lr_min              */
+    float beta1, beta2, adam_eps;  /* Adam                                 */
+    float loss_weight[4];          /* weights of the four squared errors   */
+    double psi0;         /* psi(0) for the Ewald parameters of the data     */
+} mgrav_train_cfg;
+
+/* Train on n samples: points u[n][3] in [0,1)^3 and psi[n][4] = (psi,
+ * grad psi) at them (device, double; e.g. from mgrav_ewald_psi).  Each
+ * step takes `batch` samples in an order fixed per epoch (an affine
+ * bijection of the sample index), runs forward, backward and one Adam
+ * update on the device; loss_host (nullable, host) receives the mean
+ * weighted squared error of every epoch.  Starts from the weights set by
+ * mgrav_mlp_set_weights.  Blocking. */
+mgrav_status mgrav_mlp_train(mgrav_ctx *ctx, const double *u, const double *psi, int64_t n,
+                             const mgrav_train_cfg *cfg, double *loss_host);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,16 @@ class Stats(ctypes.Structure):
                 ("graph_replay", _I)]
 
 
+class TrainConfig(ctypes.Structure):
+    _fields_ = [("epochs", _I), ("batch", _I), ("lr", ctypes.c_float),
+                ("lr_min", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+                ("loss_weight", ctypes.c_float * 4), ("psi0", _D)]
+
+
+MLP_PARAMS = 34052
+
+
 def _declare():
     L = _lib
     L.mgrav_version.restype = _I
@@ -91,6 +101,22 @@ def _declare():
     L.mgrav_compute_parts.argtypes = [_P, _I, _P, _P]
     L.mgrav_wait.restype = _I
     L.mgrav_wait.argtypes = [_P, _D, ctypes.POINTER(Stats)]
+    L.mgrav_ewald_psi.restype = _I
+    L.mgrav_ewald_psi.argtypes = [_P, _P, _I64, _D, _I, _I, _P]
+    L.mgrav_mlp_workspace_size.restype = _I
+    L.mgrav_mlp_workspace_size.argtypes = [_I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgrav_mlp_attach.restype = _I
+    L.mgrav_mlp_attach.argtypes = [_P, _P, ctypes.c_size_t, _I64]
+    L.mgrav_mlp_set_weights.restype = _I
+    L.mgrav_mlp_set_weights.argtypes = [_P, _P, _I64, _D]
+    L.mgrav_mlp_get_weights.restype = _I
+    L.mgrav_mlp_get_weights.argtypes = [_P, _P, _I64]
+    L.mgrav_mlp_forward.restype = _I
+    L.mgrav_mlp_forward.argtypes = [_P, _P, _I64, _P]
+    L.mgrav_mlp_backward.restype = _I
+    L.mgrav_mlp_backward.argtypes = [_P, _P, _P, _I64, _P]
+    L.mgrav_mlp_train.restype = _I
+    L.mgrav_mlp_train.argtypes = [_P, _P, _P, _I64, ctypes.POINTER(TrainConfig), _P]
 
 
 _declare()
@@ -101,6 +127,8 @@ EXPORTS = (
     "mgrav_destroy", "mgrav_tree_build_host", "mgrav_lists_count_host",
     "mgrav_lists_fill_host", "mgrav_workspace_size", "mgrav_bind", "mgrav_set_ewald",
     "mgrav_set_active", "mgrav_compute", "mgrav_compute_parts", "mgrav_wait",
+    "mgrav_ewald_psi", "mgrav_mlp_workspace_size", "mgrav_mlp_attach", "mgrav_mlp_set_weights",
+    "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
 )
 
 
@@ -323,6 +351,69 @@ class Context:
         st = Stats()
         _check(_lib.mgrav_wait(self._h, float(timeout_s), ctypes.byref(st)), self._h)
         return st
+
+    # ---------------------------------------------------------- surrogate
+    def ewald_psi(self, r_dev, alpha: float = 2.6, real_layers: int = 1, h2max: int = 10):
+        """psi and grad psi (unit box, unit mass) at device points r[n,3]
+        (float64); returns a device tensor [n, 4]."""
+        torch = self._torch
+        out = torch.empty((r_dev.shape[0], 4), dtype=torch.float64, device=r_dev.device)
+        self.stream.wait_stream(torch.cuda.current_stream(r_dev.device))
+        _check(_lib.mgrav_ewald_psi(self._h, _P(r_dev.data_ptr()), int(r_dev.shape[0]),
+                                    float(alpha), int(real_layers), int(h2max),
+                                    _P(out.data_ptr())), self._h)
+        torch.cuda.current_stream(r_dev.device).wait_stream(self.stream)
+        return out
+
+    def mlp_attach(self, max_batch: int = 8192):
+        torch = self._torch
+        sz = ctypes.c_size_t(0)
+        _check(_lib.mgrav_mlp_workspace_size(int(max_batch), ctypes.byref(sz)))
+        ws = torch.empty(sz.value, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        self._mlp_ws = ws
+        _check(_lib.mgrav_mlp_attach(self._h, _P(ws.data_ptr()), ctypes.c_size_t(sz.value),
+                                     int(max_batch)), self._h)
+
+    def mlp_set_weights(self, params: np.ndarray, psi0: float = 0.0):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(_lib.mgrav_mlp_set_weights(self._h, _ptr(p), int(p.size), float(psi0)), self._h)
+
+    def mlp_get_weights(self) -> np.ndarray:
+        p = np.empty(MLP_PARAMS, np.float32)
+        _check(_lib.mgrav_mlp_get_weights(self._h, _ptr(p), MLP_PARAMS), self._h)
+        return p
+
+    def mlp_forward(self, x_dev):
+        torch = self._torch
+        y = torch.empty((x_dev.shape[0], 4), dtype=torch.float32, device=x_dev.device)
+        self.stream.wait_stream(torch.cuda.current_stream(x_dev.device))
+        _check(_lib.mgrav_mlp_forward(self._h, _P(x_dev.data_ptr()), int(x_dev.shape[0]),
+                                      _P(y.data_ptr())), self._h)
+        torch.cuda.current_stream(x_dev.device).wait_stream(self.stream)
+        return y
+
+    def mlp_backward(self, x_dev, dy_dev):
+        torch = self._torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x_dev.device)
+        self.stream.wait_stream(torch.cuda.current_stream(x_dev.device))
+        _check(_lib.mgrav_mlp_backward(self._h, _P(x_dev.data_ptr()), _P(dy_dev.data_ptr()),
+                                       int(x_dev.shape[0]), _P(g.data_ptr())), self._h)
+        torch.cuda.current_stream(x_dev.device).wait_stream(self.stream)
+        return g
+
+    def mlp_train(self, u_dev, psi_dev, epochs: int, batch: int, lr: float = 2e-3,
+                  lr_min: float = 2e-5, loss_weight=(1.0, 1.0, 1.0, 1.0), psi0: float = 0.0,
+                  beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8):
+        torch = self._torch
+        cfg = TrainConfig(int(epochs), int(batch), float(lr), float(lr_min), float(beta1),
+                          float(beta2), float(adam_eps),
+                          (ctypes.c_float * 4)(*[float(w) for w in loss_weight]), float(psi0))
+        losses = np.zeros(int(epochs))
+        self.stream.wait_stream(torch.cuda.current_stream(u_dev.device))
+        _check(_lib.mgrav_mlp_train(self._h, _P(u_dev.data_ptr()), _P(psi_dev.data_ptr()),
+                                    int(u_dev.shape[0]), ctypes.byref(cfg), _ptr(losses)),
+               self._h)
+        return losses
 
     def outputs(self):
         torch = self._torch

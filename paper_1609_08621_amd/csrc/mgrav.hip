@@ -874,6 +874,25 @@ __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
     }
 }
 
+#include "mlp_kernels.inc"
+
+constexpr int kMlpMaxEpochs = 4096;
+
+struct MlpLayoutT {
+    size_t theta, m, v, grad, eff, w2f, w3f, w2b, w3b, xb, tb, dy, z1, z2, z3, a1, a2, h3, dz1,
+        dz2, dz3, tile_loss, wpart, ctl, cells, total;
+};
+
+// The surrogate network attached to a context: a caller-provided device
+// workspace holding parameters, optimiser state and training buffers.
+struct MlpState {
+    char* ws = nullptr;
+    int64_t max_batch = 0;
+    MlpLayoutT lay{};
+    bool has_weights = false;
+    double psi0 = 0.0;
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------
@@ -910,6 +929,7 @@ struct mgrav_ctx {
     struct LaunchSet* g_set = nullptr;
     bool no_graph = false;        // capture failed once: launch directly
     Control* host_ctl = nullptr;  // pinned
+    MlpState mlp;
 };
 
 // Everything a compute launches, compared byte-wise to decide whether the
@@ -917,8 +937,12 @@ struct mgrav_ctx {
 struct LaunchSet {
     RunArgs r;
     EwaldArgs e;
+    SurrogateArgs sg;
+    const int32_t* child;
+    const double* mom;
+    const double* com;
     int64_t n, n_bucket;
-    int use_mask, tree, ewald, interact_blocks;
+    int use_mask, tree, ewald, interact_blocks, surrogate_blocks;
 };
 
 namespace {
@@ -1143,11 +1167,18 @@ mgrav_status mgrav_set_ewald(mgrav_ctx* c, const mgrav_ewald* cfg) {
         c->ewald = *cfg;
         return MGRAV_OK;
     }
-    if (cfg->mode == MGRAV_EWALD_SURROGATE)
-        return fail(c, MGRAV_ERR_NOT_TRAINED, "no surrogate weights loaded");
-    if (cfg->mode != MGRAV_EWALD_EXACT) return fail(c, MGRAV_ERR_INVALID_ARG, "unknown mode");
+    if (cfg->mode != MGRAV_EWALD_EXACT && cfg->mode != MGRAV_EWALD_SURROGATE)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "unknown mode");
     if (!(c->prob.box_L > 0.0) || c->prob.n_images != 27)
         return fail(c, MGRAV_ERR_INVALID_ARG, "Ewald needs a periodic problem");
+    if (cfg->mode == MGRAV_EWALD_SURROGATE) {
+        if (!c->mlp.ws || !c->mlp.has_weights)
+            return fail(c, MGRAV_ERR_NOT_TRAINED, "no surrogate weights loaded");
+        if (cfg->top_cells != 1 && cfg->top_cells != 8 && cfg->top_cells != 64)
+            return fail(c, MGRAV_ERR_INVALID_ARG, "top_cells must be 1, 8 or 64");
+        c->ewald = *cfg;
+        return MGRAV_OK;
+    }
     if (!(cfg->alpha > 0.5 && cfg->alpha < 10.0))
         return fail(c, MGRAV_ERR_INVALID_ARG, "alpha outside (0.5, 10)");
     if (cfg->real_layers < 1 || cfg->real_layers > 4)
@@ -1191,10 +1222,34 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     L->n_bucket = p.n_bucket;
     L->use_mask = c->active ? 1 : 0;
     L->tree = (parts & (MGRAV_PART_PP | MGRAV_PART_PC)) != 0;
-    L->ewald = (parts & MGRAV_PART_EWALD) && c->ewald.mode == MGRAV_EWALD_EXACT;
+    L->ewald = (parts & MGRAV_PART_EWALD) ? c->ewald.mode : MGRAV_EWALD_NONE;
     L->interact_blocks =
         int(p.n_bucket < c->interact_blocks ? p.n_bucket : c->interact_blocks);
-    if (L->ewald) {
+    if (L->ewald == MGRAV_EWALD_SURROGATE) {
+        SurrogateArgs& g = L->sg;
+        const MlpLayoutT& ml = c->mlp.lay;
+        g.n = p.n;
+        g.pos = p.pos;
+        g.active = c->active;
+        g.cells = reinterpret_cast<const double*>(c->mlp.ws + ml.cells);
+        g.ncell = c->ewald.top_cells;
+        g.L = p.box_L;
+        g.psi0 = c->mlp.psi0;
+        g.eff = reinterpret_cast<const float*>(c->mlp.ws + ml.eff);
+        g.w2f = reinterpret_cast<const bf16x8*>(c->mlp.ws + ml.w2f);
+        g.w3f = reinterpret_cast<const bf16x8*>(c->mlp.ws + ml.w3f);
+        g.acc = acc;
+        g.pot = pot;
+        g.accumulate = L->tree;
+        L->child = p.child;
+        L->mom = p.mom;
+        L->com = p.com;
+        const int per_group = 16 / (g.ncell < 16 ? g.ncell : 16);
+        const int64_t groups = (p.n + per_group - 1) / per_group;
+        const int64_t blocks = (groups + 3) / 4;
+        L->surrogate_blocks = int(blocks < 8 * c->n_cu ? blocks : 8 * c->n_cu);
+    }
+    if (L->ewald == MGRAV_EWALD_EXACT) {
         EwaldArgs& e = L->e;
         e.n = p.n;
         e.pos = p.pos;
@@ -1218,7 +1273,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
 // 2 = Ewald.  Each phase is captured as its own graph so that timing
 // events can be recorded between them on the stream.
 static bool phase_used(const LaunchSet& L, int phase) {
-    return phase == 0 || (phase == 1 && L.tree) || (phase == 2 && L.ewald);
+    return phase == 0 || (phase == 1 && L.tree) || (phase == 2 && L.ewald != MGRAV_EWALD_NONE);
 }
 
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
@@ -1230,10 +1285,15 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     } else if (phase == 1 && L.tree) {
         hipLaunchKernelGGL(k_interact, dim3(unsigned(L.interact_blocks)), dim3(kWave), 0,
                            c->stream, L.r);
-    } else if (phase == 2 && L.ewald) {
+    } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {
         hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kWave), 0, c->stream, L.e);
         hipLaunchKernelGGL(k_ewald, dim3(unsigned((L.n + 127) / 128)), dim3(128), 0, c->stream,
                            L.e);
+    } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE) {
+        hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.mom,
+                           L.com, L.sg.ncell, const_cast<double*>(L.sg.cells));
+        hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)), dim3(256), 0,
+                           c->stream, L.sg);
     }
 }
 
@@ -1362,3 +1422,5 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
 }
 
 }  // extern "C"
+
+#include "mlp_api.inc"

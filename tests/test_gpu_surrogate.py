@@ -1,0 +1,171 @@
+"""GPU tests of the learned Ewald correction: the library's own FP64 Ewald
+point evaluation (training data), the BF16-MFMA network's forward and
+backward against the FP64 oracle with the same bf16-rounded weights, one
+Adam step, a short training run, and the surrogate compute mode."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import mlp as omlp
+
+try:
+    import torch
+except ImportError:  # pragma: no cover
+    torch = None
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mg_ctx():
+    if torch is None or not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1609_08621_amd as mg
+    ctx = mg.Context(0)
+    ctx.mlp_attach(8192)
+    yield mg, ctx
+    ctx.close()
+
+
+def dev(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else a.astype(dtype))
+    return torch.from_numpy(a).to("cuda")
+
+
+def test_ewald_psi_matches_oracle(mg_ctx):
+    mg, ctx = mg_ctx
+    rng = np.random.default_rng(12)
+    r = np.vstack([rng.uniform(-1, 1, size=(200, 3)), np.zeros((1, 3)),
+                   [[0.999, 0.999, 0.999], [1e-7, 0, 0], [0.3, 0.0, 0.0]]])
+    for alpha, R, H in [(2.6, 1, 10), (2.0, 2, 16), (3.0, 1, 4)]:
+        _case(f"ewald_psi alpha={alpha} R={R} H={H}")
+        out = ctx.ewald_psi(dev(r, np.float64), alpha, R, H).cpu().numpy()
+        ref = np.array([np.r_[d[0], d[1]] for d in
+                        (oracle.ewald_derivs(x, alpha, R, H, 1) for x in r)])
+        err = np.abs(out - ref).max()
+        print(f"  max abs err {err:.3e}", flush=True)
+        assert err < 1e-10
+
+
+def _net_inputs(n, seed):
+    return workloads.octant_points(n, seed=seed).astype(np.float32)
+
+
+def test_forward_matches_oracle(mg_ctx):
+    mg, ctx = mg_ctx
+    theta = workloads.mlp_init(17).astype(np.float32)
+    ctx.mlp_set_weights(theta)
+    for n in (1, 15, 16, 1000, 4099):
+        _case(f"mlp forward n={n}")
+        x = _net_inputs(n, 40 + n)
+        y = ctx.mlp_forward(dev(x)).cpu().numpy()
+        yo, _ = omlp.forward(theta.astype(np.float64), x.astype(np.float64), bf16=True)
+        rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+        print(f"  rel L2 {rel:.3e}", flush=True)
+        assert rel < 1e-2
+        assert np.abs(y - yo).max() < 2e-2 * np.abs(yo).max()
+
+
+def test_backward_matches_oracle(mg_ctx):
+    mg, ctx = mg_ctx
+    theta = workloads.mlp_init(18).astype(np.float32)
+    ctx.mlp_set_weights(theta)
+    n = 1024
+    x = _net_inputs(n, 77)
+    dy = np.random.default_rng(5).normal(size=(n, 4)).astype(np.float32) / n
+    _case(f"mlp backward n={n}")
+    g = ctx.mlp_backward(dev(x), dev(dy)).cpu().numpy()
+    _, cache = omlp.forward(theta.astype(np.float64), x.astype(np.float64), bf16=True)
+    go = omlp.backward(cache, dy.astype(np.float64))
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    cos = float(g @ go / (np.linalg.norm(g) * np.linalg.norm(go)))
+    print(f"  rel L2 {rel:.3e} cosine {cos:.6f}", flush=True)
+    for name, (a, b) in {"W1": (0, 384), "W2": (512, 16896), "W3": (17024, 33408),
+                         "W4": (33536, 34048), "b4": (34048, 34052)}.items():
+        rl = np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
+        print(f"  {name}: rel L2 {rl:.3e}", flush=True)
+    assert rel < 1e-2 and cos > 0.999
+
+
+def _training_data(ctx, n, seed, alpha=2.6, R=1, H=10):
+    u = workloads.octant_points(n, seed=seed)
+    psi = ctx.ewald_psi(dev(u, np.float64), alpha, R, H)
+    psi0 = float(ctx.ewald_psi(dev(np.zeros((1, 3))), alpha, R, H).cpu().numpy()[0, 0])
+    return u, dev(u, np.float64), psi, psi0
+
+
+def test_one_adam_step_matches_oracle(mg_ctx):
+    mg, ctx = mg_ctx
+    theta = workloads.mlp_init(19).astype(np.float32)
+    ctx.mlp_set_weights(theta)
+    n = 1024
+    u, u_dev, psi_dev, psi0 = _training_data(ctx, n, 91)
+    _case("mlp one Adam step")
+    w = np.array([0.5, 1.0, 1.0, 1.0])
+    ctx.mlp_train(u_dev, psi_dev, epochs=1, batch=n, lr=1e-3, lr_min=1e-3,
+                  loss_weight=w, psi0=psi0)
+    t1 = ctx.mlp_get_weights()
+    psi = psi_dev.cpu().numpy()
+    r2 = np.sum(u ** 2, 1)
+    tgt = np.c_[psi[:, 0] - psi0 + 2 * np.pi / 3 * r2, psi[:, 1:] + 4 * np.pi / 3 * u]
+    _, g = omlp.loss_grad(theta.astype(np.float64), u.astype(np.float32).astype(np.float64),
+                          tgt.astype(np.float32).astype(np.float64), w, bf16=True)
+    to, _, _ = omlp.adam_step(theta.astype(np.float64), np.zeros_like(g), np.zeros_like(g), g,
+                              1, 1e-3)
+    step_gpu = t1 - theta
+    step_ref = to - theta
+    big = np.abs(g) > 1e-3 * np.abs(g).max()  # sign-like first step: compare where |g| matters
+    agree = np.mean(np.sign(step_gpu[big]) == np.sign(step_ref[big]))
+    rel = np.linalg.norm(step_gpu[big] - step_ref[big]) / np.linalg.norm(step_ref[big])
+    print(f"  sign agreement {agree:.4f}, rel L2 of the step {rel:.3e}", flush=True)
+    assert agree > 0.99 and rel < 0.05
+
+
+def test_training_reduces_loss_and_beats_no_correction(mg_ctx):
+    mg, ctx = mg_ctx
+    ctx.mlp_set_weights(workloads.mlp_init().astype(np.float32))
+    n = 1 << 17
+    u, u_dev, psi_dev, psi0 = _training_data(ctx, n, 92)
+    _case(f"mlp training n={n}")
+    losses = ctx.mlp_train(u_dev, psi_dev, epochs=40, batch=4096, lr=3e-3, lr_min=3e-5,
+                           loss_weight=(1, 1, 1, 1), psi0=psi0)
+    print("  loss by epoch", " ".join(f"{l:.2e}" for l in losses[::5]), f"last {losses[-1]:.3e}",
+          flush=True)
+    assert losses[-1] < 0.02 * losses[0]
+    # held-out accuracy of grad psi against the exact kernel
+    uh = workloads.octant_points(20000, seed=93)
+    y = ctx.mlp_forward(dev(uh, np.float32)).cpu().numpy()
+    ex = ctx.ewald_psi(dev(uh, np.float64)).cpu().numpy()
+    g_net = y[:, 1:] - 4 * np.pi / 3 * uh
+    err = np.sqrt(np.mean(np.sum((g_net - ex[:, 1:]) ** 2, 1)))
+    scale = np.sqrt(np.mean(np.sum(ex[:, 1:] ** 2, 1)))
+    base = np.sqrt(np.mean(np.sum((-4 * np.pi / 3 * uh - ex[:, 1:]) ** 2, 1)))
+    print(f"  held-out rms |grad psi| err {err:.3e} (scale {scale:.3e}; quadratic-only "
+          f"model {base:.3e})", flush=True)
+    assert err < 0.1 * base
+
+
+def test_surrogate_compute_mode(mg_ctx):
+    mg, ctx = mg_ctx
+    ps = workloads.perturbed_lattice(16, 0.2, seed=33)
+    tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lists = oracle.build_lists(tree, 0.7, ps.eps)
+    pos_t, mass_t = ps.pos[tree.perm], ps.mass[tree.perm]
+    _case("surrogate compute mode lattice_16 (network from the previous test)")
+    ao, _ = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, 7)
+    res = {}
+    for name, ew in [("exact", None), ("none", dict(mode=mg.EWALD_NONE)),
+                     ("surrogate1", dict(mode=mg.EWALD_SURROGATE, top_cells=1)),
+                     ("surrogate8", dict(mode=mg.EWALD_SURROGATE, top_cells=8)),
+                     ("surrogate64", dict(mode=mg.EWALD_SURROGATE, top_cells=64))]:
+        ag, pg, st = mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7, ewald=ew)
+        assert np.all(np.isfinite(ag))
+        res[name] = float(np.sqrt(np.mean(np.sum((ag - ao) ** 2, 1) / np.sum(ao ** 2, 1))))
+        print(f"  {name}: rms rel acc err vs exact-Ewald oracle {res[name]:.3e}", flush=True)
+    assert res["exact"] < 1e-4
+    assert res["surrogate1"] < 0.5 * res["none"]

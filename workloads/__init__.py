@@ -117,7 +117,7 @@ def perturbed_lattice(n1d: int = 64, sigma_frac: float = 0.2,
 
 
 def halo_counts(n_halo_particles: int, n_halos: int, rng: np.random.Generator,
-                slope: float = -1.9, decades: float = 2.0) -> np.ndarray:
+                slope: float = -1.9, decades: float = 2.0):
     """Particle counts per halo: masses drawn from dN/dM ~ M^slope over
     [1, 10^decades] by inverse CDF, counts proportional to mass with the
     largest-remainder rule so they sum exactly to ``n_halo_particles``."""
@@ -222,3 +222,30 @@ def make(config: int, scale_n1d: Optional[int] = None) -> ParticleSet:
         halos = 32000 if scale_n1d is None else max(4, 32000 * n1d ** 3 // 512 ** 3)
         return clustered(n1d, halos, BASE_SEED + 5, a_max=0.005 / 4.0)
     raise ValueError(f"unknown configuration {config}")
+
+
+# Layer shapes of the Ewald-surrogate network (3 -> 128 -> 128 -> 128 -> 4),
+# in the order of its flat parameter vector.
+MLP_SHAPES = [(128, 3), (128,), (128, 128), (128,), (128, 128), (128,), (4, 128), (4,)]
+
+
+def mlp_init(seed: int = BASE_SEED + 10) -> np.ndarray:
+    """Initial parameters of the surrogate network (float64, flat): weights
+    uniform in +-1/sqrt(fan_in), biases zero.  Drawn here so the GPU
+    trainer and its reference start from the same numbers."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shp in MLP_SHAPES:
+        if len(shp) == 2:
+            b = 1.0 / math.sqrt(shp[1])
+            parts.append(rng.uniform(-b, b, size=shp).ravel())
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts)
+
+
+def octant_points(n: int, seed: int = BASE_SEED + 11) -> np.ndarray:
+    """Uniform sample points u in the fundamental octant [0, 1)^3 of the
+    unit box, where the Ewald surrogate is trained (float64 [n, 3])."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(n, 3))
