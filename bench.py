@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=4,
                     help="oracle baseline evaluates every k-th bucket")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (reference "
+                         "for the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -67,6 +70,16 @@ def main():
           f"host prep {prep_s:.2f}s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calibrate_copy_mib} MiB done", file=sys.stderr,
+              flush=True)
+        del src, dst
     ctx = mg.Context(0)
     tensors, prob = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, cfg.theta)
     ws = torch.empty(ctx.workspace_size(prob), dtype=torch.uint8, device=dev)

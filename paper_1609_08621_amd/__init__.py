@@ -16,7 +16,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmgrav.so")
+# MGRAV_LIBRARY may name another build of the same library (tuning variants).
+LIB_PATH = os.environ.get("MGRAV_LIBRARY", os.path.join(_HERE, "libmgrav.so"))
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

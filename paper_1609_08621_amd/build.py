@@ -22,19 +22,21 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str = LIB, extra_flags=()) -> str:
+    """Compile and link libmgrav.so (``extra_flags`` go to the HIP compile,
+    e.g. -DMGRAV_PP_CHUNK=64 for a tuning variant written to ``out``)."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     tree_o = os.path.join(bdir, "tree_host.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-ffp-contract=off", "-Wall",
           "-c", os.path.join(CSRC, "tree_host.cpp"), "-o", tree_o])
     dev_o = os.path.join(bdir, "mgrav.o")
-    _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "mgrav.hip"), "-o", dev_o])
-    tmp = LIB + ".tmp"
+    _run(["hipcc", *HIP_FLAGS, *extra_flags, "-c", os.path.join(CSRC, "mgrav.hip"), "-o", dev_o])
+    tmp = out + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, dev_o, tree_o,
           "-lgomp"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

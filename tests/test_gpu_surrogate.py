@@ -161,11 +161,31 @@ def test_surrogate_compute_mode(mg_ctx):
     res = {}
     for name, ew in [("exact", None), ("none", dict(mode=mg.EWALD_NONE)),
                      ("surrogate1", dict(mode=mg.EWALD_SURROGATE, top_cells=1)),
-                     ("surrogate8", dict(mode=mg.EWALD_SURROGATE, top_cells=8)),
-                     ("surrogate64", dict(mode=mg.EWALD_SURROGATE, top_cells=64))]:
+                     ("surrogate8", dict(mode=mg.EWALD_SURROGATE, top_cells=8))]:
         ag, pg, st = mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7, ewald=ew)
         assert np.all(np.isfinite(ag))
         res[name] = float(np.sqrt(np.mean(np.sum((ag - ao) ** 2, 1) / np.sum(ao ** 2, 1))))
         print(f"  {name}: rms rel acc err vs exact-Ewald oracle {res[name]:.3e}", flush=True)
     assert res["exact"] < 1e-4
     assert res["surrogate1"] < 0.5 * res["none"]
+    assert res["surrogate8"] < 0.5 * res["none"]
+
+
+@pytest.mark.skip(reason="64 top cells is switched off in the library: its one run ended in a "
+                         "device memory fault whose cause has not been found")
+def test_surrogate_64_top_cells():
+    pass
+
+
+def test_surrogate_64_top_cells_is_rejected(mg_ctx):
+    mg, ctx = mg_ctx
+    ps = workloads.perturbed_lattice(8, 0.2, seed=34)
+    tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lists = oracle.build_lists(tree, 0.7, ps.eps)
+    _case("surrogate top_cells=64 rejected on the host (no device work)")
+    tensors, p = ctx.upload(ps.pos[tree.perm], ps.mass[tree.perm], tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    with pytest.raises(mg.MgravError) as e:
+        ctx.set_ewald(mode=mg.EWALD_SURROGATE, top_cells=64)
+    assert e.value.status == mg.ERR_INVALID_ARG
+    ctx.wait(60)
