@@ -47,6 +47,8 @@ constexpr int kMaxHalfK = 1054;            // half-space wave vectors with |h|^2
 constexpr int kErrTree = 1, kErrList = 2, kErrParticle = 4;
 
 // Control block at the start of the workspace.
+constexpr int kCostBins = 64;
+
 struct Control {
     int err;
     int n_items;
@@ -56,6 +58,8 @@ struct Control {
     unsigned long long n_pc_int;
     unsigned long long n_active_p;
     unsigned long long n_active_b;
+    int bin_count[kCostBins];   // active buckets per cost bin
+    int bin_cursor[kCostBins];  // next queue slot of each bin
 };
 
 // Image shifts in units of L: id 0 the box, 1..26 lexicographic {-1,0,1}^3.
@@ -80,7 +84,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
-    size_t ctl, pdat, work, items, cellrec, ppent, pcent, ewald, total;
+    size_t ctl, pdat, work, items, bins, cellrec, ppent, pcent, ewald, total;
 };
 
 Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, int64_t n_pc) {
@@ -94,6 +98,8 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(BucketWork) * n_bucket);
     l.items = o;
     o += align256(sizeof(int) * n_bucket);
+    l.bins = o;
+    o += align256(sizeof(signed char) * n_bucket);
     l.cellrec = o;
     o += align256(sizeof(float) * kRec * n_cell);
     l.ppent = o;
@@ -326,6 +332,7 @@ struct RunArgs {
     const float4* __restrict__ pdat;
     const BucketWork* __restrict__ work;
     int* items;
+    signed char* bins;  // cost bin of each active bucket, -1 if inactive
     const float* __restrict__ cellrec;
     const float4* __restrict__ ppent;
     const float4* __restrict__ pcent;
@@ -335,17 +342,21 @@ struct RunArgs {
     int parts;
 };
 
-__global__ void k_reset(Control* ctl, int n_items_all, int use_mask) {
+__global__ void k_reset(Control* ctl) {
     if (threadIdx.x == 0) {
-        ctl->n_items = use_mask ? 0 : n_items_all;
+        ctl->n_items = 0;
         ctl->head = 0;
         ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
     }
+    if (threadIdx.x < kCostBins) ctl->bin_count[threadIdx.x] = 0;
 }
 
 // Active buckets into the work queue (in bucket order when all particles
 // are active) and the interaction counts of the active sinks.
 __global__ void __launch_bounds__(256) k_select(RunArgs a) {
+    __shared__ int hist[kCostBins];
+    if (threadIdx.x < kCostBins) hist[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     unsigned long long npp = 0, npc = 0, nact = 0, nb = 0;
     if (b < a.n_bucket) {
@@ -355,12 +366,16 @@ __global__ void __launch_bounds__(256) k_select(RunArgs a) {
             na = 0;
             for (int k = 0; k < wk.nsink; ++k) na += a.active[wk.first + k] != 0;
         }
-        if (a.active == nullptr) {
-            a.items[b] = int(b);
-        } else if (na > 0) {
-            const int slot = atomicAdd(&a.ctl->n_items, 1);
-            a.items[slot] = int(b);
+        int bin = -1;
+        if (na > 0) {
+            // work of the bucket in FLOP, binned by its base-2 logarithm
+            const unsigned long long cost =
+                (unsigned long long)wk.nsink *
+                ((unsigned long long)wk.nsrc * 20ull + (unsigned long long)(wk.pc1 - wk.pc0) * 242ull);
+            bin = 63 - __clzll(cost | 1ull);
+            atomicAdd(&hist[bin], 1);
         }
+        a.bins[b] = (signed char)bin;
         if (na > 0) {
             nact = na;
             nb = 1;
@@ -384,6 +399,8 @@ __global__ void __launch_bounds__(256) k_select(RunArgs a) {
         red[3][w] = nb;
     }
     __syncthreads();
+    if (threadIdx.x < kCostBins && hist[threadIdx.x])
+        atomicAdd(&a.ctl->bin_count[threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 0) {
         unsigned long long s[4] = {0, 0, 0, 0};
         for (int i = 0; i < int(blockDim.x / kWave); ++i)
@@ -395,6 +412,27 @@ __global__ void __launch_bounds__(256) k_select(RunArgs a) {
             atomicAdd(&a.ctl->n_active_b, s[3]);
         }
     }
+}
+
+// Queue order: most expensive cost bins first (longest processing time
+// first, to within a factor 2), so the persistent kernel ends on short items.
+__global__ void k_order_scan(Control* ctl) {
+    if (threadIdx.x != 0) return;
+    int off = 0;
+    for (int q = kCostBins - 1; q >= 0; --q) {
+        ctl->bin_cursor[q] = off;
+        off += ctl->bin_count[q];
+    }
+    ctl->n_items = off;
+}
+
+__global__ void __launch_bounds__(256) k_order_scatter(RunArgs a) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= a.n_bucket) return;
+    const int bin = a.bins[b];
+    if (bin < 0) return;
+    const int slot = atomicAdd(&a.ctl->bin_cursor[bin], 1);
+    a.items[slot] = int(b);
 }
 
 // Order-4 PC expansion of one cell at one point, float.
@@ -486,6 +524,19 @@ __device__ __forceinline__ void pc_one(const float (&r)[kRec], float cx, float c
     A.z += S * z + a2 * g2z + a3 * g3z + a4x4 * v4z;
 }
 
+// Load of a wave-uniform element of memory that no kernel running at the
+// same time writes: through the constant address space the compiler emits a
+// scalar load into scalar registers.  (The host compilation pass only needs
+// the function to exist.)
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p, int64_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) T*)p)[i];
+#else
+    return p[i];
+#endif
+}
+
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
     for (int o = 1; o < kWave; o <<= 1) {
         const int t = __shfl_up(v, o);
@@ -503,35 +554,46 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(MGRAV_INTERACT_WAVES, 8))) k_interact(RunArgs a) {
     __shared__ float4 lds[kLdsSrc];
+    __shared__ int4 etab[kChunk];    // per PP entry of a fill: LDS base, count, first
+    __shared__ float4 edel[kChunk];  // per PP entry of a fill: source-sink offset
     const int lane = threadIdx.x;
+    const int n_items = __builtin_amdgcn_readfirstlane(
+        __atomic_load_n(&a.ctl->n_items, __ATOMIC_RELAXED));  // fixed by earlier kernels
+    int item = 0;
+    if (lane == 0) item = atomicAdd(&a.ctl->head, 1);
+    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(&a.ctl->head, 1);
-        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-        const int n_items = __builtin_amdgcn_readfirstlane(
-            __atomic_load_n(&a.ctl->n_items, __ATOMIC_RELAXED));
         if (item >= n_items) break;
-        const int b = __builtin_amdgcn_readfirstlane(a.items[item]);
-        const BucketWork* wk = a.work + b;
-        const int first = __builtin_amdgcn_readfirstlane(wk->first);
-        const int nsink = __builtin_amdgcn_readfirstlane(wk->nsink);
-        if (nsink <= 0) continue;
+        // claim the next queue slot now; its latency hides behind this item
+        int next = 0;
+        if (lane == 0) next = atomicAdd(&a.ctl->head, 1);
+        const int b = load_uniform(a.items, item);
+        const BucketWork wk = load_uniform(a.work, b);
+        const int first = wk.first;
+        const int nsink = wk.nsink;
+        if (nsink <= 0) {
+            item = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
+            continue;
+        }
 
+        // The bucket's sink particles are wave-uniform: read them through the
+        // constant address space so they arrive as scalar loads, all in flight
+        // together, straight into scalar registers.
         float sx[kBucket], sy[kBucket], sz[kBucket];
 #pragma unroll
         for (int i = 0; i < kBucket; ++i) {
             const int p = first + (i < nsink ? i : nsink - 1);
-            const float4 q = a.pdat[p];
-            sx[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q.x)));
-            sy[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q.y)));
-            sz[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q.z)));
+            const float4 q = load_uniform(a.pdat, p);
+            sx[i] = q.x;
+            sy[i] = q.y;
+            sz[i] = q.z;
         }
         Acc4 acc[kBucket];
 #pragma unroll
         for (int i = 0; i < kBucket; ++i) acc[i] = Acc4{0.f, 0.f, 0.f, 0.f};
 
         if (a.parts & MGRAV_PART_PP) {
-            const int64_t e0 = wk->pp0, e1 = wk->pp1;
+            const int64_t e0 = wk.pp0, e1 = wk.pp1;
             for (int64_t c0 = e0; c0 < e1; c0 += kChunk) {
                 const int64_t e = c0 + lane;
                 int cnt = 0, sfirst = 0;
@@ -547,9 +609,38 @@ __global__ void __launch_bounds__(kWave)
                 const int incl = wave_incl_scan(cnt, lane);
                 const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
                 const int base = incl - cnt;
-                for (int k = 0; k < cnt; ++k) {
-                    const float4 q = a.pdat[sfirst + k];
-                    lds[base + k] = make_float4(q.x + ent.x, q.y + ent.y, q.z + ent.z, q.w);
+                // Cooperative copy of the chunk's source particles into LDS:
+                // the entry table goes to LDS, then each step moves 4 entries
+                // (16 lanes each, one particle per lane; an entry's particles
+                // are contiguous).  Four steps are unrolled with unconditional
+                // loads (inactive lanes read particle 0) so that four loads per
+                // lane are in flight at once.
+                if (lane < kChunk) {
+                    etab[lane] = make_int4(base, cnt, sfirst, 0);
+                    edel[lane] = ent;
+                }
+                __syncthreads();
+                const int nent = int(e1 - c0 < kChunk ? e1 - c0 : kChunk);
+                const int eg = lane >> 4, ek = lane & 15;
+                for (int j0 = 0; j0 < nent; j0 += 16) {
+                    float4 q[4];
+                    int4 tb[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = j0 + 4 * u + eg;
+                        tb[u] = e < nent ? etab[e] : make_int4(0, 0, 0, 0);
+                        const int src = ek < tb[u].y ? tb[u].z + ek : 0;
+                        q[u] = a.pdat[src];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = j0 + 4 * u + eg;
+                        if (ek < tb[u].y) {
+                            const float4 d = edel[e];
+                            lds[tb[u].x + ek] =
+                                make_float4(q[u].x + d.x, q[u].y + d.y, q[u].z + d.z, q[u].w);
+                        }
+                    }
                 }
                 __syncthreads();
                 for (int t0 = 0; t0 < total; t0 += kWave) {
@@ -564,7 +655,7 @@ __global__ void __launch_bounds__(kWave)
             }
         }
         if (a.parts & MGRAV_PART_PC) {
-            const int64_t f0 = wk->pc0, f1 = wk->pc1;
+            const int64_t f0 = wk.pc0, f1 = wk.pc1;
             for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
                 const int64_t f = c0 + lane;
                 float r[kRec];
@@ -621,7 +712,7 @@ __global__ void __launch_bounds__(kWave)
             const int p = first + i;
             if (a.active == nullptr || a.active[p]) {
                 float val = v[0];
-                if (comp == 3 && (a.parts & MGRAV_PART_PP) && wk->self) {
+                if (comp == 3 && (a.parts & MGRAV_PART_PP) && wk.self) {
                     // remove the self pair, which entered as -m_i / eps
                     const float4 q = a.pdat[p];
                     const float D = fmaf(0.f, 0.f, fmaf(0.f, 0.f, fmaf(0.f, 0.f, a.eps2)));
@@ -631,6 +722,7 @@ __global__ void __launch_bounds__(kWave)
                 out[p] = val;
             }
         }
+        item = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
     }
 }
 
@@ -745,6 +837,32 @@ __global__ void k_ewald_setup(EwaldArgs a) {
 // by the downward recurrence g_n = -(r^2 g_{n+1} + k_{n+1} e^{-alpha^2 r^2})
 // / (2n+1) with k_m = (-2 alpha^2)^m / (alpha sqrt(pi)); otherwise upward
 // from the closed form (the same recurrence solved for g_{n+1}).
+// 1/(2j + 11) and 1/(j + 1) for the power series, 1/(2n + 1) for the
+// downward recurrence: constants, so the loops below divide nothing.
+struct EwaldConsts {
+    double inv_odd[30];   // 1 / (2j + 11)
+    double inv_next[30];  // 1 / (j + 1)
+    double inv_2n1[6];    // 1 / (2n + 1)
+};
+__constant__ EwaldConsts c_ew = {
+    {1.0 / 11, 1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21, 1.0 / 23, 1.0 / 25, 1.0 / 27,
+     1.0 / 29, 1.0 / 31, 1.0 / 33, 1.0 / 35, 1.0 / 37, 1.0 / 39, 1.0 / 41, 1.0 / 43, 1.0 / 45,
+     1.0 / 47, 1.0 / 49, 1.0 / 51, 1.0 / 53, 1.0 / 55, 1.0 / 57, 1.0 / 59, 1.0 / 61, 1.0 / 63,
+     1.0 / 65, 1.0 / 67, 1.0 / 69},
+    {1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,
+     1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18,
+     1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
+     1.0 / 28, 1.0 / 29, 1.0 / 30},
+    {1.0 / 1, 1.0 / 3, 1.0 / 5, 1.0 / 7, 1.0 / 9, 1.0 / 11}};
+
+// Radial derivatives g_n = ((1/r) d/dr)^n of erf(alpha r)/r (near images)
+// or of -erfc(alpha r)/r (outer real-space shells), n = 0..5, unit box.
+// Near images with alpha r < sqrt(2): g_5 from its power series
+//   g_5 = (2 alpha/sqrt(pi)) (-2 alpha^2)^5 sum_j (-x)^j / (j! (2j + 11)),
+//   x = alpha^2 r^2,
+// the rest by the downward recurrence g_n = -(r^2 g_{n+1} + k_{n+1} e^{-x})
+// / (2n+1) with k_m = (-2 alpha^2)^m / (alpha sqrt(pi)); otherwise upward
+// from the closed form (the same recurrence solved for g_{n+1}).
 __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
     const double SQRT_PI = 1.77245385090551602729;
     const double al2 = alpha * alpha;
@@ -752,27 +870,33 @@ __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
     const double E = exp(-x);
     double k[6];
     k[0] = 1.0 / (alpha * SQRT_PI);
+#pragma unroll
     for (int m = 1; m < 6; ++m) k[m] = k[m - 1] * (-2.0 * al2);
-    if (near) {
-        if (x < 2.0) {
-            double s = 0.0, term = 1.0;
-            for (int j = 0; j < 30; ++j) {
-                s += term / double(2 * j + 11);
-                term *= -x / double(j + 1);
-            }
-            g[5] = 2.0 * alpha / SQRT_PI * (-32.0 * al2 * al2 * al2 * al2 * al2) * s;
-            for (int n = 4; n >= 0; --n) g[n] = -(r2 * g[n + 1] + k[n + 1] * E) / double(2 * n + 1);
-        } else {
-            const double r = sqrt(r2);
-            g[0] = erf(alpha * r) / r;
-            for (int n = 0; n < 5; ++n) g[n + 1] = -(double(2 * n + 1) * g[n] + k[n + 1] * E) / r2;
+    if (near && x < 2.0) {
+        double sum = 0.0, term = 1.0;
+#pragma unroll
+        for (int j = 0; j < 30; ++j) {
+            sum = fma(term, c_ew.inv_odd[j], sum);
+            term *= -x * c_ew.inv_next[j];
         }
+        g[5] = 2.0 * alpha / SQRT_PI * (-32.0 * al2 * al2 * al2 * al2 * al2) * sum;
+#pragma unroll
+        for (int n = 4; n >= 0; --n) g[n] = -(r2 * g[n + 1] + k[n + 1] * E) * c_ew.inv_2n1[n];
+        return;
+    }
+    const double r = sqrt(r2);
+    const double inv_r = 1.0 / r;
+    const double inv_r2 = inv_r * inv_r;
+    if (near) {
+        g[0] = erf(alpha * r) * inv_r;
+#pragma unroll
+        for (int n = 0; n < 5; ++n) g[n + 1] = -(double(2 * n + 1) * g[n] + k[n + 1] * E) * inv_r2;
     } else {
-        const double r = sqrt(r2);
-        double e = erfc(alpha * r) / r;
+        double e = erfc(alpha * r) * inv_r;
         g[0] = -e;
+#pragma unroll
         for (int n = 0; n < 5; ++n) {
-            e = (-double(2 * n + 1) * e + k[n + 1] * E) / r2;
+            e = (k[n + 1] * E - double(2 * n + 1) * e) * inv_r2;
             g[n + 1] = -e;
         }
     }
@@ -780,7 +904,7 @@ __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
 
 struct TableRec {
     const double* t;
-    __device__ double operator[](int i) const { return t[i]; }
+    __device__ double operator[](int i) const { return load_uniform(t, i); }
 };
 
 __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
@@ -830,7 +954,7 @@ __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
         czm = t;
     }
     const double* tab = a.table + 64;
-    const int nk = int(a.table[44]);
+    const int nk = int(load_uniform(a.table, 44));
     int q = 0;
     double cxh = 1.0, sxh = 0.0;  // e^{i 2 pi hx x}
     for (int hx = 0; hx <= hm; ++hx) {
@@ -842,11 +966,11 @@ __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
                 const int h2 = hx * hx + hy * hy + hz * hz;
                 const bool half = hx > 0 || hy > 0 || (hy == 0 && hz > 0);
                 if (h2 > 0 && h2 <= a.h2max && half && q < nk) {
-                    const double* row = tab + 8 * q;
+                    const int row = 8 * q;
                     ++q;
                     const double c = cxy * czh - sxy * szh, s = sxy * czh + cxy * szh;
-                    phi += row[3] * c + row[4] * s;
-                    const double f = row[5] * s + row[6] * c;
+                    phi += load_uniform(tab, row + 3) * c + load_uniform(tab, row + 4) * s;
+                    const double f = load_uniform(tab, row + 5) * s + load_uniform(tab, row + 6) * c;
                     ax += f * double(hx);
                     ay += f * double(hy);
                     az += f * double(hz);
@@ -863,7 +987,7 @@ __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
         sxh = sxh * c1x + cxh * s1x;
         cxh = t;
     }
-    phi += a.table[45];
+    phi += load_uniform(a.table, 45);
     // physical units: potential / L, acceleration / L^2
     phi *= invL;
     const double invL2 = invL * invL;
@@ -1227,6 +1351,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     r.pdat = reinterpret_cast<const float4*>(w + c->lay.pdat);
     r.work = reinterpret_cast<const BucketWork*>(w + c->lay.work);
     r.items = reinterpret_cast<int*>(w + c->lay.items);
+    r.bins = reinterpret_cast<signed char*>(w + c->lay.bins);
     r.cellrec = reinterpret_cast<const float*>(w + c->lay.cellrec);
     r.ppent = reinterpret_cast<const float4*>(w + c->lay.ppent);
     r.pcent = reinterpret_cast<const float4*>(w + c->lay.pcent);
@@ -1294,10 +1419,12 @@ static bool phase_used(const LaunchSet& L, int phase) {
 
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     if (phase == 0) {
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
-                           int(L.n_bucket), L.use_mask);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
         hipLaunchKernelGGL(k_select, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256), 0,
                            c->stream, L.r);
+        hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
+        hipLaunchKernelGGL(k_order_scatter, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256),
+                           0, c->stream, L.r);
     } else if (phase == 1 && L.tree) {
         hipLaunchKernelGGL(k_interact, dim3(unsigned(L.interact_blocks)), dim3(kWave), 0,
                            c->stream, L.r);
