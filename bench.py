@@ -12,6 +12,7 @@ Prints one JSON line.  The metric is PP + PC interactions per second;
 times the FP64 oracle on a bounded sample of the same buckets.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +39,11 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=4,
                     help="oracle baseline evaluates every k-th bucket")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ewald-study", action="store_true",
+                    help="instead of the throughput line: exact vs learned Ewald correction, "
+                         "time against force error, on the chosen config (default 4)")
+    ap.add_argument("--train-samples", type=int, default=2_000_000)
+    ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -58,6 +64,9 @@ def main():
     import paper_1609_08621_amd as mg
     import workloads
 
+    if args.ewald_study:
+        ewald_study(args)
+        return
     cfg = workloads.CONFIGS[args.config]
     ps = workloads.make(args.config)
     t0 = time.perf_counter()
@@ -150,13 +159,50 @@ def main():
             "flop_per_pp": FLOP_PP,
             "flop_per_pc": FLOP_PC,
             "traffic": None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
         },
     }
 
+    detail = interact_traffic(cfg.name)
+    if detail is not None:
+        out["roofline"]["traffic"] = detail.pop("bytes_per_launch")
+        out["roofline"]["traffic_detail"] = detail
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc, pot)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "k_interact_lattice_64cubed_counters.json")
+
+
+def interact_source_digest() -> str:
+    """Digest of the interact kernel's source (from ``struct RunArgs`` to
+    the Ewald section of mgrav.hip): counters taken on other code are stale."""
+    with open(os.path.join(ROOT, "paper_1609_08621_amd", "csrc", "mgrav.hip")) as f:
+        src = f.read()
+    a, b = src.index("struct RunArgs {"), src.index("// Ewald correction (FP64)")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def interact_traffic(workload: str):
+    """HBM bytes per k_interact launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
+    None when the summary is missing, for another workload, or taken on
+    different kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or rec.get("source_digest") != interact_source_digest():
+        return None
+    return {"bytes_per_launch": rec["traffic_bytes_per_launch"],
+            "fetch_kib_raw": rec["fetch_kib_per_dispatch"],
+            "write_kib_raw": rec["write_kib_per_dispatch"],
+            "fetch_factor": rec["fetch_factor"], "write_factor": rec["write_factor"],
+            "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
@@ -197,6 +243,103 @@ def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
         "gpu_rms_rel_acc_err_vs_oracle": err,
         "gpu_rel_pot_err_vs_oracle": perr,
     }
+
+
+def ewald_study(args):
+    """Exact Ewald variants (order, k-space cut-off) against the learned
+    correction (root or 8 top cells): time of the Ewald phase against the
+    rms error of the corrected acceleration, relative to the total force,
+    with a converged exact correction as reference.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1609_08621_amd as mg
+    import workloads
+
+    cnum = args.config if args.config != 2 else 4
+    cfg = workloads.CONFIGS[cnum]
+    ps = workloads.make(cnum)
+    t0 = time.perf_counter()
+    tree = mg.tree_build(ps.pos, ps.mass, ps.box_L, cfg.bucket)
+    lists = mg.lists_build(tree, cfg.theta, ps.eps)
+    print(f"[ewald] {cfg.name}: n={ps.n} host prep {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    ctx = mg.Context(0)
+    tensors, prob = ctx.upload(ps.pos[tree.perm], ps.mass[tree.perm], tree, lists, ps.eps,
+                               cfg.theta)
+    ws = torch.empty(ctx.workspace_size(prob), dtype=torch.uint8, device=dev)
+    acc = torch.zeros(3 * ps.n, dtype=torch.float32, device=dev)
+    pot = torch.zeros(ps.n, dtype=torch.float32, device=dev)
+    ctx.bind(prob, tensors, ws)
+
+    def run(parts, ew, reps=5):
+        ctx.set_ewald(**ew)
+        ms = []
+        for _ in range(reps):
+            ctx.compute(acc, pot, parts)
+            st = ctx.wait(120.0)
+            ms.append(st.ms_ewald if parts == mg.PART_EWALD else st.ms_interact)
+        torch.cuda.synchronize()
+        return acc.view(3, -1).double().clone(), float(np.median(ms))
+
+    exact = dict(mode=mg.EWALD_EXACT)
+    a_tree, ms_tree = run(mg.PART_PP | mg.PART_PC, dict(exact, alpha=2.6, real_layers=1,
+                                                         h2max=10, order=4), reps=2)
+    a_ref, _ = run(mg.PART_EWALD, dict(exact, alpha=2.0, real_layers=2, h2max=36, order=4), 1)
+    a_tot = a_tree + a_ref
+    norm = (a_tot ** 2).sum(0)
+
+    def err(a_corr):
+        return float(torch.sqrt(torch.mean(((a_corr - a_ref) ** 2).sum(0) / norm)))
+
+    rows = []
+    none_err = err(torch.zeros_like(a_ref))
+    for order in (0, 2, 4):
+        for h2 in (0, 1, 2, 3, 4, 6, 10):
+            for alpha in (2.0, 2.6):
+                a_c, ms = run(mg.PART_EWALD, dict(exact, alpha=alpha, real_layers=1, h2max=h2,
+                                                  order=order))
+                rows.append(dict(kind="exact", order=order, h2max=h2, alpha=alpha, ms=ms,
+                                 err=err(a_c)))
+    # train the surrogate on the library's own exact kernel (alpha 2.6, |h|^2 <= 10)
+    u = torch.from_numpy(workloads.octant_points(args.train_samples)).to(dev)
+    psi = ctx.ewald_psi(u, 2.6, 1, 10)
+    psi0 = float(ctx.ewald_psi(torch.zeros((1, 3), dtype=torch.float64, device=dev), 2.6, 1,
+                               10).cpu()[0, 0])
+    ctx.mlp_attach(8192)
+    ctx.mlp_set_weights(workloads.mlp_init().astype(np.float32))
+    t0 = time.perf_counter()
+    losses = ctx.mlp_train(u, psi, epochs=args.train_epochs, batch=8192, lr=3e-3, lr_min=3e-5,
+                           psi0=psi0)
+    train_s = time.perf_counter() - t0
+    for top in (1, 8, 64):
+        a_c, ms = run(mg.PART_EWALD, dict(mode=mg.EWALD_SURROGATE, top_cells=top))
+        rows.append(dict(kind="surrogate", top_cells=top, ms=ms, err=err(a_c)))
+    ex = sorted([r for r in rows if r["kind"] == "exact"], key=lambda r: r["ms"])
+    front, best = [], float("inf")
+    for r in ex:  # Pareto front of the exact variants: faster and more accurate
+        if r["err"] < best:
+            front.append(r)
+            best = r["err"]
+    verdict = []
+    for r in rows:
+        if r["kind"] != "surrogate":
+            continue
+        ok = [f for f in front if f["err"] <= r["err"]]
+        cheapest = min(ok, key=lambda f: f["ms"]) if ok else None
+        verdict.append(dict(top_cells=r["top_cells"], surrogate_ms=r["ms"], surrogate_err=r["err"],
+                            exact_ms_at_equal_or_better_err=None if cheapest is None else cheapest["ms"],
+                            exact_variant=cheapest,
+                            surrogate_faster=None if cheapest is None else r["ms"] < cheapest["ms"]))
+    out = dict(metric="Ewald correction: time vs rms force error (relative to total force)",
+               config=dict(workload=cfg.name, n=ps.n, theta=cfg.theta),
+               reference="exact, alpha 2.0, real layers 2, |h|^2 <= 36, order 4",
+               no_correction_err=none_err, tree_kernel_ms=ms_tree, train_seconds=train_s,
+               train_samples=args.train_samples, train_epochs=args.train_epochs,
+               final_loss=float(losses[-1]), variants=rows, pareto_exact=front, verdict=verdict)
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

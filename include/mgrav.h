@@ -215,9 +215,10 @@ mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace,
  * force).  mode NONE switches the correction off (open boundaries need
  * nothing); EXACT uses the sums above.  SURROGATE evaluates the trained
  * network of mgrav_mlp_* instead: the field of the monopoles of the
- * `top_cells` (1 = root, or 8) tree cells at depth log2(top_cells),
- * psi from the network at every (particle, cell) pair, added in double.
- * SURROGATE without weights fails NOT_TRAINED. */
+ * `top_cells` (1 = root, 8 or 64) tree cells at depth log2(top_cells)
+ * (a leaf met earlier stands for its branch), psi from the network at
+ * every (particle, cell) pair, added in double.  SURROGATE without weights
+ * fails NOT_TRAINED; another top_cells value fails INVALID_ARG. */
 typedef enum {
     MGRAV_EWALD_NONE = 0,
     MGRAV_EWALD_EXACT = 1,
@@ -230,7 +231,7 @@ typedef struct {
     int real_layers;   /* |n|_inf <= real_layers in real space (>= 1)      */
     int h2max;         /* k-space terms with 0 < |h|^2 <= h2max (0..64)    */
     int order;         /* 0, 2 or 4 (moments of the root used)             */
-    int top_cells;     /* surrogate: 1 = root monopole, or 8 cells         */
+    int top_cells;     /* surrogate: 1 = root monopole, 8 or 64 cells      */
 } mgrav_ewald;
 
 /* Defaults after bind: EXACT with alpha 2.6, real_layers 1, h2max 10,

@@ -436,11 +436,13 @@ int64_t orc_tree_build(int64_t n, const double *pos, const double *mass, double 
     tb_cell(&t, 0, n, lo, hi, 0);
     free(t.tmp);
     if (t.overflow) return -1;
-    int64_t nb = 0;
-    for (int64_t c = 0; c < t.ncell; ++c) {
+    /* cells are independent: each is computed from its own particles */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < t.ncell; ++c)
         cell_properties(c, pos, mass, perm, cell_first, cell_count, com, bmax, bbox, mom);
+    int64_t nb = 0;
+    for (int64_t c = 0; c < t.ncell; ++c)
         if (child[2 * c] < 0) bucket_cell[nb++] = (int32_t)c;
-    }
     *n_bucket = nb;
     return t.ncell;
 }

@@ -118,7 +118,7 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
 struct StageArgs {
     int64_t n, n_cell, n_bucket, n_pp, n_pc;
     int n_images;
-    double L;
+    double L, eps;
     const double* __restrict__ pos;
     const double* __restrict__ mass;
     const int64_t* __restrict__ cell_first;
@@ -200,7 +200,31 @@ __global__ void k_stage_particles(StageArgs a) {
     }
 }
 
-// (2) cells: float coefficients of the order-4 expansion (see pc_terms).
+// Inverse of the length unit in which a cell's PC interactions are
+// evaluated: 2^-e with 2^e the smallest power of two above both the
+// softening length and the distance from the centre of mass to the
+// farthest corner of the bounding box.  In this unit the radial
+// derivatives of order up to 5 stay O(1) for every accepted cell (they
+// would overflow float for small cells a few softening lengths away), and
+// since the unit is a power of two the rescaling itself rounds nothing.
+__device__ float cell_inv_unit(const StageArgs& a, int64_t c) {
+    const double* bb = a.bbox + 6 * c;
+    const double* x = a.com + 3 * c;
+    double r2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double d = fmax(x[k] - bb[k], bb[3 + k] - x[k]);
+        r2 += d * d;
+    }
+    const double b = fmax(sqrt(r2), a.eps);
+    int e = 0;
+    (void)frexp(b, &e);                 // b < 2^e
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);  // NaN or absurd boxes stay finite
+    return float(ldexp(1.0, -e));
+}
+
+// (2) cells: float coefficients of the order-4 expansion (see pc_terms),
+// the order-k ones in units of the cell's length unit (times t^k), and
+// t = 1 / unit in the last word.
 __global__ void k_stage_cells(StageArgs a) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
@@ -221,7 +245,13 @@ __global__ void k_stage_cells(StageArgs a) {
     r[26] = 0.25 * (m[21] + m[28] + m[30]);
     r[27] = 0.25 * (m[22] + m[29] + m[31]);
     for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0;
-    r[43] = 0.0;
+    const double t = cell_inv_unit(a, c), t2 = t * t, t3 = t2 * t, t4 = t3 * t;
+    for (int i = 1; i < 8; ++i) r[i] *= t2;
+    for (int i = 8; i < 11; ++i) r[i] *= t3;
+    r[11] *= t4;
+    for (int i = 12; i < 22; ++i) r[i] *= t3;
+    for (int i = 22; i < kRec - 1; ++i) r[i] *= t4;
+    r[43] = t;
     float4* out = reinterpret_cast<float4*>(a.cellrec + kRec * c);
     for (int i = 0; i < kRec / 4; ++i)
         out[i] = make_float4(float(r[4 * i]), float(r[4 * i + 1]), float(r[4 * i + 2]),
@@ -286,7 +316,8 @@ __global__ void __launch_bounds__(kWave) k_stage_pp(StageArgs a) {
 }
 
 // (3b) PC entries: offset of the source's centre of mass (plus image
-// shift) from the sink bucket's centre; the cell index in the fourth word.
+// shift) from the sink bucket's centre, in the cell's length unit; the cell
+// index in the fourth word.  Reads the cell records, so it runs after (2).
 __global__ void __launch_bounds__(kWave) k_stage_pc(StageArgs a) {
     const int64_t b = blockIdx.x;
     const int lane = threadIdx.x;
@@ -304,9 +335,10 @@ __global__ void __launch_bounds__(kWave) k_stage_pc(StageArgs a) {
             // an invalid entry becomes a massless cell at the bucket centre
             float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
             if (sink_ok && src >= 0 && src < a.n_cell && img < a.n_images) {
-                out.x = float(a.com[3 * src] + c_shift[img][0] * a.L - C[0]);
-                out.y = float(a.com[3 * src + 1] + c_shift[img][1] * a.L - C[1]);
-                out.z = float(a.com[3 * src + 2] + c_shift[img][2] * a.L - C[2]);
+                const float t = cell_inv_unit(a, src);
+                out.x = float(a.com[3 * src] + c_shift[img][0] * a.L - C[0]) * t;
+                out.y = float(a.com[3 * src + 1] + c_shift[img][1] * a.L - C[1]) * t;
+                out.z = float(a.com[3 * src + 2] + c_shift[img][2] * a.L - C[2]) * t;
                 out.w = __int_as_float(int(src));
             } else {
                 bad = 1;
@@ -426,13 +458,24 @@ __global__ void k_order_scan(Control* ctl) {
     ctl->n_items = off;
 }
 
+// Block-aggregated scatter: one global atomic per (block, bin) reserves a
+// range of queue slots; ranks inside the block come from LDS atomics.
 __global__ void __launch_bounds__(256) k_order_scatter(RunArgs a) {
+    __shared__ int cnt[kCostBins];
+    __shared__ int base[kCostBins];
+    if (threadIdx.x < kCostBins) cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= a.n_bucket) return;
-    const int bin = a.bins[b];
-    if (bin < 0) return;
-    const int slot = atomicAdd(&a.ctl->bin_cursor[bin], 1);
-    a.items[slot] = int(b);
+    int bin = -1, rank = 0;
+    if (b < a.n_bucket) {
+        bin = a.bins[b];
+        if (bin >= 0) rank = atomicAdd(&cnt[bin], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCostBins && cnt[threadIdx.x] > 0)
+        base[threadIdx.x] = atomicAdd(&a.ctl->bin_cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (bin >= 0) a.items[base[bin] + rank] = int(b);
 }
 
 // Order-4 PC expansion of one cell at one point, float.
@@ -503,12 +546,18 @@ __device__ __forceinline__ void pp_one(float sx, float sy, float sz, float m, fl
     A.z = fmaf(mw3, dz, A.z);
 }
 
-__device__ __forceinline__ void pc_one(const float (&r)[kRec], float cx, float cy, float cz,
-                                       float px, float py, float pz, float eps2, Acc4& A) {
-    const float x = px - cx, y = py - cy, z = pz - cz;  // R = sink - centre
-    const float D = fmaf(x, x, fmaf(y, y, fmaf(z, z, eps2)));
-    const float a0 = __builtin_amdgcn_rsqf(D);
-    const float u = -(a0 * a0);
+// In the cell's length unit 1/t: R' = t R (the centre offset c arrives
+// scaled), eps2t = t^2 eps^2, moments of order k times t^k.  Then
+// phi = t phi'(R') and acc = t^2 acc'(R'): one factor t is folded into a_n,
+// the other into the accumulation.
+__device__ __forceinline__ void pc_one(const float (&r)[kRec], float t, float cx, float cy,
+                                       float cz, float px, float py, float pz, float eps2t,
+                                       Acc4& A) {
+    const float x = fmaf(px, t, -cx), y = fmaf(py, t, -cy), z = fmaf(pz, t, -cz);
+    const float D = fmaf(x, x, fmaf(y, y, fmaf(z, z, eps2t)));
+    const float w = __builtin_amdgcn_rsqf(D);
+    const float a0 = w * t;
+    const float u = -(w * w);
     const float a1 = a0 * u;
     const float a2 = a1 * (3.f * u);
     const float a3 = a2 * (5.f * u);
@@ -519,9 +568,9 @@ __device__ __forceinline__ void pc_one(const float (&r)[kRec], float cx, float c
     A.p -= a0 * r[0] + a1 * r[1] + a2 * P2 + a3 * P3 + a4 * P4;
     const float S = a1 * r[0] + a2 * r[1] + a3 * P2 + a4 * P3 + a5 * P4;
     const float a4x4 = 4.f * a4;
-    A.x += S * x + a2 * g2x + a3 * g3x + a4x4 * v4x;
-    A.y += S * y + a2 * g2y + a3 * g3y + a4x4 * v4y;
-    A.z += S * z + a2 * g2z + a3 * g3z + a4x4 * v4z;
+    A.x = fmaf(t, S * x + a2 * g2x + a3 * g3x + a4x4 * v4x, A.x);
+    A.y = fmaf(t, S * y + a2 * g2y + a3 * g3y + a4x4 * v4y, A.y);
+    A.z = fmaf(t, S * z + a2 * g2z + a3 * g3z + a4x4 * v4z, A.z);
 }
 
 // Load of a wave-uniform element of memory that no kernel running at the
@@ -659,14 +708,18 @@ __global__ void __launch_bounds__(kWave)
             for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
                 const int64_t f = c0 + lane;
                 float r[kRec];
-                float cx = 0.f, cy = 0.f, cz = 0.f;  // padding: zero moments at the centre
+                // padding and invalid entries: zero moments one unit away
+                // (t = 0 makes R' = (1, 0, 0) and D' = 1, all terms finite)
+                float cx = -1.f, cy = 0.f, cz = 0.f;
                 int cell = -1;
                 if (f < f1) {
                     const float4 ent = a.pcent[f];
-                    cx = ent.x;
-                    cy = ent.y;
-                    cz = ent.z;
                     cell = __float_as_int(ent.w);
+                    if (cell >= 0) {
+                        cx = ent.x;
+                        cy = ent.y;
+                        cz = ent.z;
+                    }
                 }
                 if (cell >= 0) {
                     const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
@@ -682,9 +735,11 @@ __global__ void __launch_bounds__(kWave)
 #pragma unroll
                     for (int i = 0; i < kRec; ++i) r[i] = 0.f;
                 }
+                const float t = r[kRec - 1];
+                const float eps2t = a.eps2 * t * t;
 #pragma unroll
                 for (int i = 0; i < kBucket; ++i)
-                    if (i < nsink) pc_one(r, cx, cy, cz, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                    if (i < nsink) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
             }
         }
 
@@ -757,86 +812,106 @@ __constant__ int c_ax4[15][4] = {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0
 
 // Root coefficients in unit-box scaling (order k scaled by L^-k), masked
 // by the requested order, and the k-space table for the half space of
-// wave vectors (each row stands for h and -h).
-__global__ void k_ewald_setup(EwaldArgs a) {
-    if (threadIdx.x != 0) return;
+// wave vectors (each row stands for h and -h).  One block: the candidate
+// vectors h (hx >= 0, |hy|, |hz| <= hmax, in lexicographic order) are
+// taken 256 at a time, one per thread, and compacted by a block prefix
+// sum, so the table order does not depend on the thread count.
+constexpr int kSetupThreads = 256;
+__global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
     const double* m = a.mom;
     const double L = a.L, L2 = L * L, L3 = L2 * L, L4 = L3 * L;
-    double r[kRec];
-    r[0] = m[0];
-    r[1] = 0.5 * (m[1] + m[4] + m[6]) / L2;
-    for (int i = 0; i < 6; ++i) r[2 + i] = 0.5 * m[1 + i] / L2;
-    r[8] = -0.5 * (m[7] + m[10] + m[12]) / L3;
-    r[9] = -0.5 * (m[8] + m[13] + m[15]) / L3;
-    r[10] = -0.5 * (m[9] + m[14] + m[16]) / L3;
-    r[11] = 0.125 * (m[17] + m[27] + m[31] + 2.0 * (m[20] + m[22] + m[29])) / L4;
-    for (int i = 0; i < 10; ++i) r[12 + i] = -m[7 + i] / 6.0 / L3;
-    r[22] = 0.25 * (m[17] + m[20] + m[22]) / L4;
-    r[23] = 0.25 * (m[18] + m[23] + m[25]) / L4;
-    r[24] = 0.25 * (m[19] + m[24] + m[26]) / L4;
-    r[25] = 0.25 * (m[20] + m[27] + m[29]) / L4;
-    r[26] = 0.25 * (m[21] + m[28] + m[30]) / L4;
-    r[27] = 0.25 * (m[22] + m[29] + m[31]) / L4;
-    for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0 / L4;
-    r[43] = 0.0;
-    if (a.order < 4) {  // drop orders 3 and 4 (and their traces)
-        for (int i = 8; i < 11; ++i) r[i] = 0.0;
-        r[11] = 0.0;
-        for (int i = 12; i < kRec; ++i) r[i] = 0.0;
+    if (threadIdx.x == 0) {
+        double r[kRec];
+        r[0] = m[0];
+        r[1] = 0.5 * (m[1] + m[4] + m[6]) / L2;
+        for (int i = 0; i < 6; ++i) r[2 + i] = 0.5 * m[1 + i] / L2;
+        r[8] = -0.5 * (m[7] + m[10] + m[12]) / L3;
+        r[9] = -0.5 * (m[8] + m[13] + m[15]) / L3;
+        r[10] = -0.5 * (m[9] + m[14] + m[16]) / L3;
+        r[11] = 0.125 * (m[17] + m[27] + m[31] + 2.0 * (m[20] + m[22] + m[29])) / L4;
+        for (int i = 0; i < 10; ++i) r[12 + i] = -m[7 + i] / 6.0 / L3;
+        r[22] = 0.25 * (m[17] + m[20] + m[22]) / L4;
+        r[23] = 0.25 * (m[18] + m[23] + m[25]) / L4;
+        r[24] = 0.25 * (m[19] + m[24] + m[26]) / L4;
+        r[25] = 0.25 * (m[20] + m[27] + m[29]) / L4;
+        r[26] = 0.25 * (m[21] + m[28] + m[30]) / L4;
+        r[27] = 0.25 * (m[22] + m[29] + m[31]) / L4;
+        for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0 / L4;
+        r[43] = 0.0;
+        if (a.order < 4) {  // drop orders 3 and 4 (and their traces)
+            for (int i = 8; i < 11; ++i) r[i] = 0.0;
+            r[11] = 0.0;
+            for (int i = 12; i < kRec; ++i) r[i] = 0.0;
+        }
+        if (a.order < 2) {
+            for (int i = 1; i < kRec; ++i) r[i] = 0.0;
+        }
+        for (int i = 0; i < kRec; ++i) a.table[i] = r[i];
+        a.table[45] = m[0] * 3.14159265358979323846 / (a.alpha * a.alpha);  // background
     }
-    if (a.order < 2) {
-        for (int i = 1; i < kRec; ++i) r[i] = 0.0;
-    }
-    for (int i = 0; i < kRec; ++i) a.table[i] = r[i];
 
     // k-space: phi += -(1/pi) sum_h c_h (A_h cos th + B_h sin th), th = 2 pi h.r,
     // c_h = exp(-pi^2 h^2 / alpha^2) / h^2, A_h = M - 2 pi^2 Q2 + 2 pi^4/3 Q4,
     // B_h = -4 pi^3/3 Q3, Q_k = M_k[h..h] (unit-box moments).
     const double PI = 3.14159265358979323846;
-    const int hm = a.hmax;
-    int nk = 0;
+    const int hm = a.hmax, side = 2 * hm + 1;
+    const int n_cand = (hm + 1) * side * side;
+    __shared__ int wave_total[kSetupThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     double* tab = a.table + 64;
-    for (int hx = 0; hx <= hm; ++hx)
-        for (int hy = -hm; hy <= hm; ++hy)
-            for (int hz = -hm; hz <= hm; ++hz) {
-                const int h2 = hx * hx + hy * hy + hz * hz;
-                if (h2 == 0 || h2 > a.h2max) continue;
-                if (hx == 0 && (hy < 0 || (hy == 0 && hz < 0))) continue;  // half space
-                if (nk >= kMaxHalfK) continue;
-                const double h[3] = {double(hx), double(hy), double(hz)};
-                double Q2 = 0, Q3 = 0, Q4 = 0;
-                for (int q = 0; q < 6; ++q) Q2 += c_m2[q] * m[1 + q] / L2 * h[c_ax2[q][0]] * h[c_ax2[q][1]];
-                for (int q = 0; q < 10; ++q)
-                    Q3 += c_m3[q] * m[7 + q] / L3 * h[c_ax3[q][0]] * h[c_ax3[q][1]] * h[c_ax3[q][2]];
-                for (int q = 0; q < 15; ++q)
-                    Q4 += c_m4[q] * m[17 + q] / L4 * h[c_ax4[q][0]] * h[c_ax4[q][1]] *
-                          h[c_ax4[q][2]] * h[c_ax4[q][3]];
-                if (a.order < 4) Q3 = Q4 = 0.0;
-                if (a.order < 2) Q2 = 0.0;
-                const double A = m[0] - 2.0 * PI * PI * Q2 + 2.0 * PI * PI * PI * PI / 3.0 * Q4;
-                const double B = -4.0 * PI * PI * PI / 3.0 * Q3;
-                const double c = exp(-PI * PI * h2 / (a.alpha * a.alpha)) / h2;
-                double* row = tab + 8 * nk;
-                row[0] = h[0];
-                row[1] = h[1];
-                row[2] = h[2];
-                row[3] = -(2.0 / PI) * c * A;  // cos coefficient of phi (pair doubled)
-                row[4] = -(2.0 / PI) * c * B;  // sin coefficient of phi
-                row[5] = -4.0 * c * A;         // sin coefficient of acc / h
-                row[6] = 4.0 * c * B;          // cos coefficient of acc / h
-                row[7] = 0.0;
-                ++nk;
-            }
-    a.table[44] = double(nk);
-    a.table[45] = m[0] * PI / (a.alpha * a.alpha);  // background constant
+    int nk = 0;
+    for (int c0 = 0; c0 < n_cand; c0 += kSetupThreads) {
+        const int cidx = c0 + int(threadIdx.x);
+        int hx = 0, hy = 0, hz = 0;
+        bool keep = false;
+        if (cidx < n_cand) {
+            hx = cidx / (side * side);
+            hy = (cidx / side) % side - hm;
+            hz = cidx % side - hm;
+            const int h2 = hx * hx + hy * hy + hz * hz;
+            keep = h2 != 0 && h2 <= a.h2max && !(hx == 0 && (hy < 0 || (hy == 0 && hz < 0)));
+        }
+        const unsigned long long mask = __ballot(keep);
+        const int in_wave = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_total[w] = __popcll(mask);
+        __syncthreads();
+        int before = nk;
+        for (int q = 0; q < w; ++q) before += wave_total[q];
+        int chunk = 0;
+        for (int q = 0; q < kSetupThreads / kWave; ++q) chunk += wave_total[q];
+        __syncthreads();  // wave_total is rewritten by the next chunk
+        const int slot = before + in_wave;
+        if (keep && slot < kMaxHalfK) {
+            const int h2 = hx * hx + hy * hy + hz * hz;
+            const double h[3] = {double(hx), double(hy), double(hz)};
+            double Q2 = 0, Q3 = 0, Q4 = 0;
+            for (int q = 0; q < 6; ++q)
+                Q2 += c_m2[q] * m[1 + q] / L2 * h[c_ax2[q][0]] * h[c_ax2[q][1]];
+            for (int q = 0; q < 10; ++q)
+                Q3 += c_m3[q] * m[7 + q] / L3 * h[c_ax3[q][0]] * h[c_ax3[q][1]] * h[c_ax3[q][2]];
+            for (int q = 0; q < 15; ++q)
+                Q4 += c_m4[q] * m[17 + q] / L4 * h[c_ax4[q][0]] * h[c_ax4[q][1]] *
+                      h[c_ax4[q][2]] * h[c_ax4[q][3]];
+            if (a.order < 4) Q3 = Q4 = 0.0;
+            if (a.order < 2) Q2 = 0.0;
+            const double A = m[0] - 2.0 * PI * PI * Q2 + 2.0 * PI * PI * PI * PI / 3.0 * Q4;
+            const double B = -4.0 * PI * PI * PI / 3.0 * Q3;
+            const double cc = exp(-PI * PI * h2 / (a.alpha * a.alpha)) / h2;
+            double* row = tab + 8 * slot;
+            row[0] = h[0];
+            row[1] = h[1];
+            row[2] = h[2];
+            row[3] = -(2.0 / PI) * cc * A;  // cos coefficient of phi (pair doubled)
+            row[4] = -(2.0 / PI) * cc * B;  // sin coefficient of phi
+            row[5] = -4.0 * cc * A;         // sin coefficient of acc / h
+            row[6] = 4.0 * cc * B;          // cos coefficient of acc / h
+            row[7] = 0.0;
+        }
+        nk += chunk;
+    }
+    if (threadIdx.x == 0) a.table[44] = double(nk < kMaxHalfK ? nk : kMaxHalfK);
 }
 
-// Radial derivatives g_n = ((1/r) d/dr)^n of erf(alpha r)/r (near images)
-// or of -erfc(alpha r)/r (outer real-space shells), n = 0..5, unit box.
-// Near images with alpha r < sqrt(2): g_5 from its power series, the rest
-// by the downward recurrence g_n = -(r^2 g_{n+1} + k_{n+1} e^{-alpha^2 r^2})
-// / (2n+1) with k_m = (-2 alpha^2)^m / (alpha sqrt(pi)); otherwise upward
-// from the closed form (the same recurrence solved for g_{n+1}).
 // 1/(2j + 11) and 1/(j + 1) for the power series, 1/(2n + 1) for the
 // downward recurrence: constants, so the loops below divide nothing.
 struct EwaldConsts {
@@ -1077,7 +1152,7 @@ struct LaunchSet {
     const int32_t* child;
     const double* mom;
     const double* com;
-    int64_t n, n_bucket;
+    int64_t n, n_bucket, n_cell;
     int use_mask, tree, ewald, interact_blocks, surrogate_blocks;
 };
 
@@ -1120,6 +1195,7 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.n_pc = p.n_pc;
     a.n_images = p.n_images;
     a.L = p.box_L;
+    a.eps = p.eps;
     a.pos = p.pos;
     a.mass = p.mass;
     a.cell_first = p.cell_first;
@@ -1312,10 +1388,8 @@ mgrav_status mgrav_set_ewald(mgrav_ctx* c, const mgrav_ewald* cfg) {
     if (cfg->mode == MGRAV_EWALD_SURROGATE) {
         if (!c->mlp.ws || !c->mlp.has_weights)
             return fail(c, MGRAV_ERR_NOT_TRAINED, "no surrogate weights loaded");
-        // 64 top cells is switched off: one run of that mode ended in a device
-        // memory fault whose cause has not been found (see the design notes)
-        if (cfg->top_cells != 1 && cfg->top_cells != 8)
-            return fail(c, MGRAV_ERR_INVALID_ARG, "top_cells must be 1 or 8");
+        if (cfg->top_cells != 1 && cfg->top_cells != 8 && cfg->top_cells != 64)
+            return fail(c, MGRAV_ERR_INVALID_ARG, "top_cells must be 1, 8 or 64");
         c->ewald = *cfg;
         return MGRAV_OK;
     }
@@ -1385,6 +1459,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         L->child = p.child;
         L->mom = p.mom;
         L->com = p.com;
+        L->n_cell = p.n_cell;
         const int per_group = 16 / (g.ncell < 16 ? g.ncell : 16);
         const int64_t groups = (p.n + per_group - 1) / per_group;
         const int64_t blocks = (groups + 3) / 4;
@@ -1429,12 +1504,12 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         hipLaunchKernelGGL(k_interact, dim3(unsigned(L.interact_blocks)), dim3(kWave), 0,
                            c->stream, L.r);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {
-        hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kWave), 0, c->stream, L.e);
+        hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->stream, L.e);
         hipLaunchKernelGGL(k_ewald, dim3(unsigned((L.n + 127) / 128)), dim3(128), 0, c->stream,
                            L.e);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE) {
-        hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.mom,
-                           L.com, L.sg.ncell, const_cast<double*>(L.sg.cells));
+        hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.com,
+                           L.mom, L.n_cell, L.sg.ncell, const_cast<double*>(L.sg.cells));
         hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)), dim3(256), 0,
                            c->stream, L.sg);
     }

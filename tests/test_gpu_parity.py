@@ -59,25 +59,37 @@ def gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts=7, theta=0.7, ewald=None, 
 
 
 def check_parts(mg_ctx, ps, label, sample=None):
+    """PP, PC, Ewald and all parts on one bound problem (uploaded once), each
+    against the oracle on the same tree and lists; with ``sample`` only every
+    sample-th sink bucket is evaluated by the oracle and compared."""
+    mg, ctx = mg_ctx
     tree, lists, pos_t, mass_t = prepared(ps)
-    mg = mg_ctx[0]
     res = {}
     parts_list = [(mg.PART_PP, "PP"), (mg.PART_PC, "PC"), (mg.PART_ALL, "ALL")]
     if ps.box_L > 0:
         parts_list.insert(2, (mg.PART_EWALD, "EWALD"))
     sel = None
+    idx = slice(None)
     if sample is not None:
         sel = np.arange(0, tree.n_bucket, sample, dtype=np.int32)
+        idx = np.concatenate([np.arange(tree.cell_first[c], tree.cell_first[c] + tree.cell_count[c])
+                              for c in tree.bucket_cell[sel]])
+    _case(f"{label} n={ps.n} upload + bind (buckets={tree.n_bucket}, pp={lists.pp_src.size}, "
+          f"pc={lists.pc_src.size})")
+    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    acc, pot = ctx.outputs()
     pot_scale = {}
     for parts, name in parts_list:
         _case(f"{label} n={ps.n} parts={name} sample={sample}")
-        ag, pg, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts)
+        ctx.compute(acc, pot, parts)
+        st = ctx.wait(120)
+        ag = acc.cpu().numpy().reshape(3, -1).T[idx]
+        pg = pot.cpu().numpy()[idx]
         ao, po = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, parts, buckets=sel)
-        if sel is not None:
-            idx = np.concatenate([np.arange(tree.cell_first[c], tree.cell_first[c] + tree.cell_count[c])
-                                  for c in tree.bucket_cell[sel]])
-            ag, pg, ao, po = ag[idx], pg[idx], ao[idx], po[idx]
-        assert np.all(np.isfinite(ag)) and np.all(np.isfinite(pg))
+        ao, po = ao[idx], po[idx]
+        bad = int(np.sum(~np.isfinite(ag).all(1) | ~np.isfinite(pg)))
+        assert bad == 0, f"{name}: {bad} sinks with non-finite results"
         pot_scale[name] = po
         if name == "ALL":
             ref = pot_scale["PP"] + pot_scale["PC"]
@@ -86,8 +98,8 @@ def check_parts(mg_ctx, ps, label, sample=None):
             perr = glob_rel(pg[:, None], po[:, None])
         res[name] = (rel_rms(ag, ao), glob_rel(ag, ao), perr)
         print(f"  {name}: rel_rms={res[name][0]:.3e} glob={res[name][1]:.3e} "
-              f"pot={res[name][2]:.3e}  pp={st.n_pp_interactions} pc={st.n_pc_interactions}",
-              flush=True)
+              f"pot={res[name][2]:.3e}  pp={st.n_pp_interactions} pc={st.n_pc_interactions} "
+              f"graph={st.graph_replay}", flush=True)
     assert res["PP"][1] < TOL_PART and res["PC"][1] < TOL_PART
     if "EWALD" in res:
         assert res["EWALD"][1] < TOL_EWALD and res["EWALD"][2] < TOL_EWALD
@@ -108,8 +120,60 @@ def test_clustered_periodic_small(mg_ctx):
     check_parts(mg_ctx, workloads.make(3, scale_n1d=24), "clustered_24")
 
 
+def test_tight_clusters_small_softening(mg_ctx):
+    """Sinks within a few softening lengths of small accepted cells, and
+    bucket centres within 5e-5 of a sink: the order-5 radial derivative of
+    the PC expansion, 945 D^-11/2, exceeds the float range there unless each
+    cell is evaluated in its own length unit (regression: NaN before)."""
+    ps = workloads.clustered(16, 4, a_max=0.002, eps=5e-5)
+    check_parts(mg_ctx, ps, "tight_clusters_16_eps5e-5")
+
+
 def test_lattice_periodic_full_size_sampled(mg_ctx):
     check_parts(mg_ctx, workloads.make(2), "lattice_64_full", sample=97)
+
+
+def test_clustered_full_size_sampled(mg_ctx):
+    # 128^3 = 2,097,152 particles in 500 haloes + background (uneven lists)
+    check_parts(mg_ctx, workloads.make(3), "clustered_128_full", sample=1361)
+
+
+def test_lattice_256_full_size_sampled(mg_ctx):
+    # 256^3 = 16,777,216 particles, sigma = 0.3 spacing
+    check_parts(mg_ctx, workloads.make(4), "lattice_256_full", sample=10007)
+
+
+def test_active_subsets_full_size(mg_ctx):
+    """Clustered 128^3: 10 % and 1 % active (largest |a|) against the full run."""
+    mg, ctx = mg_ctx
+    ps = workloads.make(3)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    _case("clustered_128_full full run, then 10% and 1% active")
+    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    acc, pot = ctx.outputs()
+    ctx.compute(acc, pot)
+    st_full = ctx.wait(120)
+    a_full = acc.cpu().numpy().reshape(3, -1).T.copy()
+    p_full = pot.cpu().numpy().copy()
+    dev = torch.device("cuda", 0)
+    for frac in (0.1, 0.01):
+        active = workloads.active_by_acceleration(np.linalg.norm(a_full, axis=1), frac)
+        ctx.set_active(torch.from_numpy(active).to(dev))
+        acc2 = torch.full((3 * ps.n,), -3.0, dtype=torch.float32, device=dev)
+        pot2 = torch.full((ps.n,), -3.0, dtype=torch.float32, device=dev)
+        ctx.compute(acc2, pot2)
+        st = ctx.wait(120)
+        a = acc2.cpu().numpy().reshape(3, -1).T
+        pa = pot2.cpu().numpy()
+        on = active.astype(bool)
+        print(f"  {frac:.0%}: active={on.sum()} buckets={st.n_active_buckets} "
+              f"pp={st.n_pp_interactions} pc={st.n_pc_interactions} ms={st.ms_total:.3f} "
+              f"(full {st_full.ms_total:.3f})", flush=True)
+        assert st.n_active_particles == on.sum()
+        assert np.array_equal(a[on], a_full[on]) and np.array_equal(pa[on], p_full[on])
+        assert np.all(a[~on] == -3.0) and np.all(pa[~on] == -3.0)
+    ctx.set_active(None)
 
 
 def test_unperturbed_lattice_cancellation(mg_ctx):

@@ -150,6 +150,34 @@ def test_training_reduces_loss_and_beats_no_correction(mg_ctx):
     assert err < 0.1 * base
 
 
+def test_surrogate_correction_matches_network(mg_ctx):
+    """The surrogate Ewald correction alone (root monopole) equals the network
+    evaluated by mlp_forward on the folded offsets, unfolded on the host."""
+    mg, ctx = mg_ctx
+    ps = workloads.perturbed_lattice(16, 0.2, seed=33)
+    tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lists = oracle.build_lists(tree, 0.7, ps.eps)
+    pos_t, mass_t = ps.pos[tree.perm], ps.mass[tree.perm]
+    _case("surrogate correction alone vs mlp_forward (network from the training test)")
+    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    ctx.set_ewald(mode=mg.EWALD_SURROGATE, top_cells=1)
+    acc, pot = ctx.outputs()
+    ctx.compute(acc, pot, mg.PART_EWALD)
+    ctx.wait(60)
+    a_gpu = acc.cpu().numpy().reshape(3, -1).T
+    r = pos_t - tree.com[0]
+    u = np.abs(r).astype(np.float32)
+    y = ctx.mlp_forward(dev(u)).cpu().numpy().astype(np.float64)
+    g = y[:, 1:] - 4 * np.pi / 3 * u.astype(np.float64)
+    a_exp = -tree.mom[0, 0] * np.sign(r) * g
+    err = np.abs(a_gpu - a_exp).max() / np.abs(a_exp).max()
+    cos = float(np.sum(a_gpu * a_exp) / np.sqrt(np.sum(a_gpu ** 2) * np.sum(a_exp ** 2)))
+    print(f"  max rel diff {err:.3e}, cosine {cos:.6f}; first rows gpu {a_gpu[:2]} "
+          f"expected {a_exp[:2]}", flush=True)
+    assert err < 1e-4
+
+
 def test_surrogate_compute_mode(mg_ctx):
     mg, ctx = mg_ctx
     ps = workloads.perturbed_lattice(16, 0.2, seed=33)
@@ -171,21 +199,37 @@ def test_surrogate_compute_mode(mg_ctx):
     assert res["surrogate8"] < 0.5 * res["none"]
 
 
-@pytest.mark.skip(reason="64 top cells is switched off in the library: its one run ended in a "
-                         "device memory fault whose cause has not been found")
-def test_surrogate_64_top_cells():
-    pass
+def test_surrogate_64_top_cells(mg_ctx):
+    """64 top cells: the cell table holds depth-6 cells of the node-left-right
+    numbering, whose indices reach the end of the cell arrays (regression:
+    the table kernel once had the centre-of-mass and moment arrays swapped,
+    reading the 3-double-per-cell array at 32 doubles per cell)."""
+    mg, ctx = mg_ctx
+    ps = workloads.perturbed_lattice(16, 0.2, seed=33)
+    tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lists = oracle.build_lists(tree, 0.7, ps.eps)
+    pos_t, mass_t = ps.pos[tree.perm], ps.mass[tree.perm]
+    _case("surrogate top_cells=64 lattice_16 (network from the training test)")
+    ao, _ = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, 7)
+    an, _, _ = mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7,
+                        ewald=dict(mode=mg.EWALD_NONE))
+    ag, pg, _ = mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7,
+                         ewald=dict(mode=mg.EWALD_SURROGATE, top_cells=64))
+    assert np.all(np.isfinite(ag)) and np.all(np.isfinite(pg))
+    err = lambda a: float(np.sqrt(np.mean(np.sum((a - ao) ** 2, 1) / np.sum(ao ** 2, 1))))
+    print(f"  surrogate64 {err(ag):.3e}, none {err(an):.3e}", flush=True)
+    assert err(ag) < 0.5 * err(an)
 
 
-def test_surrogate_64_top_cells_is_rejected(mg_ctx):
+def test_surrogate_bad_top_cells_is_rejected(mg_ctx):
     mg, ctx = mg_ctx
     ps = workloads.perturbed_lattice(8, 0.2, seed=34)
     tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
     lists = oracle.build_lists(tree, 0.7, ps.eps)
-    _case("surrogate top_cells=64 rejected on the host (no device work)")
+    _case("surrogate top_cells=4 rejected on the host (no device work)")
     tensors, p = ctx.upload(ps.pos[tree.perm], ps.mass[tree.perm], tree, lists, ps.eps, 0.7)
     ctx.bind(p, tensors)
     with pytest.raises(mg.MgravError) as e:
-        ctx.set_ewald(mode=mg.EWALD_SURROGATE, top_cells=64)
+        ctx.set_ewald(mode=mg.EWALD_SURROGATE, top_cells=4)
     assert e.value.status == mg.ERR_INVALID_ARG
     ctx.wait(60)
