@@ -335,7 +335,8 @@ __global__ void __launch_bounds__(kWave) k_stage_pc(StageArgs a) {
             // an invalid entry becomes a massless cell at the bucket centre
             float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
             if (sink_ok && src >= 0 && src < a.n_cell && img < a.n_images) {
-                const float t = cell_inv_unit(a, src);
+                // the cell's 1/unit, staged by k_stage_cells (launched before)
+                const float t = a.cellrec[kRec * src + kRec - 1];
                 out.x = float(a.com[3 * src] + c_shift[img][0] * a.L - C[0]) * t;
                 out.y = float(a.com[3 * src + 1] + c_shift[img][1] * a.L - C[1]) * t;
                 out.z = float(a.com[3 * src + 2] + c_shift[img][2] * a.L - C[2]) * t;
@@ -495,25 +496,30 @@ __device__ __forceinline__ void multipole_terms(const Rec& r, T x, T y, T z, T& 
     const T xx = x * x, yy = y * y, zz = z * z;
     const T x2 = x + x, y2 = y + y;
     const T qxy = x2 * y, qxz = x2 * z, qyz = y2 * z;
-    // order 2 (with the traced parts of orders 3 and 4)
-    const T v2x = r[2] * x + r[3] * y + r[4] * z;
-    const T v2y = r[3] * x + r[5] * y + r[6] * z;
-    const T v2z = r[4] * x + r[6] * y + r[7] * z;
-    P2 = x * (v2x + r[8]) + y * (v2y + r[9]) + z * (v2z + r[10]) + r[11];
-    g2x = v2x + v2x + r[8];
-    g2y = v2y + v2y + r[9];
-    g2z = v2z + v2z + r[10];
-    // order 3 (with the once-traced part of order 4)
-    const T v3x = r[12] * xx + r[15] * yy + r[17] * zz + r[13] * qxy + r[14] * qxz + r[16] * qyz;
-    const T v3y = r[13] * xx + r[18] * yy + r[20] * zz + r[15] * qxy + r[16] * qxz + r[19] * qyz;
-    const T v3z = r[14] * xx + r[19] * yy + r[21] * zz + r[16] * qxy + r[17] * qxz + r[20] * qyz;
+    // order 2 (with the traced parts of orders 3 and 4): h2 = M2/2 R + r8..10,
+    // each chain started from its constant so that it is all FMAs
+    const T h2x = r[2] * x + (r[3] * y + (r[4] * z + r[8]));
+    const T h2y = r[3] * x + (r[5] * y + (r[6] * z + r[9]));
+    const T h2z = r[4] * x + (r[6] * y + (r[7] * z + r[10]));
+    P2 = x * h2x + y * h2y + z * h2z + r[11];
+    g2x = T(2) * h2x - r[8];  // 2 (M2/2 R) + r8
+    g2y = T(2) * h2y - r[9];
+    g2z = T(2) * h2z - r[10];
+    // order 3 (with the once-traced part of order 4): h3 = v3 + w4, the v3
+    // chain started from w4
     const T w4x = r[22] * x + r[23] * y + r[24] * z;
     const T w4y = r[23] * x + r[25] * y + r[26] * z;
     const T w4z = r[24] * x + r[26] * y + r[27] * z;
-    P3 = x * (v3x + w4x) + y * (v3y + w4y) + z * (v3z + w4z);
-    g3x = T(3) * v3x + (w4x + w4x);
-    g3y = T(3) * v3y + (w4y + w4y);
-    g3z = T(3) * v3z + (w4z + w4z);
+    const T h3x = r[12] * xx + (r[15] * yy + (r[17] * zz + (r[13] * qxy + (r[14] * qxz +
+                  (r[16] * qyz + w4x)))));
+    const T h3y = r[13] * xx + (r[18] * yy + (r[20] * zz + (r[15] * qxy + (r[16] * qxz +
+                  (r[19] * qyz + w4y)))));
+    const T h3z = r[14] * xx + (r[19] * yy + (r[21] * zz + (r[16] * qxy + (r[17] * qxz +
+                  (r[20] * qyz + w4z)))));
+    P3 = x * h3x + y * h3y + z * h3z;
+    g3x = T(3) * h3x - w4x;  // 3 v3 + 2 w4
+    g3y = T(3) * h3y - w4y;
+    g3z = T(3) * h3z - w4z;
     // order 4: cubic monomials with their multiplicities folded in
     const T x3 = T(3) * x, y3 = T(3) * y, z3 = T(3) * z;
     const T cxxx = xx * x, cxxy = xx * y3, cxxz = xx * z3, cxyy = yy * x3, cxyz = qxy * z3;
@@ -558,16 +564,19 @@ __device__ __forceinline__ void pc_one(const float (&r)[kRec], float t, float cx
     const float w = __builtin_amdgcn_rsqf(D);
     const float a0 = w * t;
     const float u = -(w * w);
+    const float u3 = 3.f * u, u5 = 5.f * u, u7 = 7.f * u, u9 = 9.f * u;
     const float a1 = a0 * u;
-    const float a2 = a1 * (3.f * u);
-    const float a3 = a2 * (5.f * u);
-    const float a4 = a3 * (7.f * u);
-    const float a5 = a4 * (9.f * u);
+    const float a2 = a1 * u3;
+    const float a3 = a2 * u5;
+    const float a4x4 = a3 * (4.f * u7);
     float P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
     multipole_terms<float>(r, x, y, z, P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z);
-    A.p -= a0 * r[0] + a1 * r[1] + a2 * P2 + a3 * P3 + a4 * P4;
-    const float S = a1 * r[0] + a2 * r[1] + a3 * P2 + a4 * P3 + a5 * P4;
-    const float a4x4 = 4.f * a4;
+    // a_n = a0 u^n (2n-1)!!, so both radial sums nest (Horner in u):
+    //   sum_n a_n P_n     = a0 (M + u (P1 + 3u (P2 + 5u (P3 + 7u P4)))),
+    //   sum_n a_{n+1} P_n = a1 (M + 3u (P1 + 5u (P2 + 7u (P3 + 9u P4)))).
+    const float hp = fmaf(u, fmaf(u3, fmaf(u5, fmaf(u7, P4, P3), P2), r[1]), r[0]);
+    A.p = fmaf(-a0, hp, A.p);
+    const float S = a1 * fmaf(u3, fmaf(u5, fmaf(u7, fmaf(u9, P4, P3), P2), r[1]), r[0]);
     A.x = fmaf(t, S * x + a2 * g2x + a3 * g3x + a4x4 * v4x, A.x);
     A.y = fmaf(t, S * y + a2 * g2y + a3 * g3y + a4x4 * v4y, A.y);
     A.z = fmaf(t, S * z + a2 * g2z + a3 * g3z + a4x4 * v4z, A.z);
@@ -584,6 +593,41 @@ __device__ __forceinline__ T load_uniform(const T* p, int64_t i) {
 #else
     return p[i];
 #endif
+}
+
+// PC entry f of a list ending at f1: the cell's offset (in its length
+// unit) and its record.  Entries at or past f1, and invalid cells, give zero
+// moments one unit away (t = 0 makes R' = (1, 0, 0) and D' = 1, so every
+// term is finite and adds zero).
+__device__ __forceinline__ void load_pc(const RunArgs& a, int64_t f, int64_t f1, float (&r)[kRec],
+                                        float& cx, float& cy, float& cz) {
+    cx = -1.f;
+    cy = 0.f;
+    cz = 0.f;
+    int cell = -1;
+    if (f < f1) {
+        const float4 ent = a.pcent[f];
+        cell = __float_as_int(ent.w);
+        if (cell >= 0) {
+            cx = ent.x;
+            cy = ent.y;
+            cz = ent.z;
+        }
+    }
+    if (cell >= 0) {
+        const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
+#pragma unroll
+        for (int i = 0; i < kRec / 4; ++i) {
+            const float4 q = rec[i];
+            r[4 * i] = q.x;
+            r[4 * i + 1] = q.y;
+            r[4 * i + 2] = q.z;
+            r[4 * i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kRec; ++i) r[i] = 0.f;
+    }
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -706,35 +750,8 @@ __global__ void __launch_bounds__(kWave)
         if (a.parts & MGRAV_PART_PC) {
             const int64_t f0 = wk.pc0, f1 = wk.pc1;
             for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
-                const int64_t f = c0 + lane;
-                float r[kRec];
-                // padding and invalid entries: zero moments one unit away
-                // (t = 0 makes R' = (1, 0, 0) and D' = 1, all terms finite)
-                float cx = -1.f, cy = 0.f, cz = 0.f;
-                int cell = -1;
-                if (f < f1) {
-                    const float4 ent = a.pcent[f];
-                    cell = __float_as_int(ent.w);
-                    if (cell >= 0) {
-                        cx = ent.x;
-                        cy = ent.y;
-                        cz = ent.z;
-                    }
-                }
-                if (cell >= 0) {
-                    const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
-#pragma unroll
-                    for (int i = 0; i < kRec / 4; ++i) {
-                        const float4 q = rec[i];
-                        r[4 * i] = q.x;
-                        r[4 * i + 1] = q.y;
-                        r[4 * i + 2] = q.z;
-                        r[4 * i + 3] = q.w;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < kRec; ++i) r[i] = 0.f;
-                }
+                float r[kRec], cx, cy, cz;
+                load_pc(a, c0 + lane, f1, r, cx, cy, cz);
                 const float t = r[kRec - 1];
                 const float eps2t = a.eps2 * t * t;
 #pragma unroll
@@ -905,7 +922,9 @@ __global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
             row[4] = -(2.0 / PI) * cc * B;  // sin coefficient of phi
             row[5] = -4.0 * cc * A;         // sin coefficient of acc / h
             row[6] = 4.0 * cc * B;          // cos coefficient of acc / h
-            row[7] = 0.0;
+            // the axis indices for the phase tables of k_ewald
+            reinterpret_cast<int64_t*>(row)[7] =
+                int64_t(hx) | (int64_t(hy + hm) << 8) | (int64_t(hz + hm) << 16);
         }
         nk += chunk;
     }
@@ -982,7 +1001,17 @@ struct TableRec {
     __device__ double operator[](int i) const { return load_uniform(t, i); }
 };
 
-__global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
+// Dynamic LDS of k_ewald: per thread, (hmax + 1) + 2 (2 hmax + 1) complex
+// phase factors.  Blocks of 128 threads up to hmax = 5 (57 KB), 64 above
+// (at most 44 KB at hmax = 8), so a block never needs more than 64 KB.
+constexpr int kEwaldThreads = 128;
+inline int ewald_threads(int hmax) { return hmax <= 5 ? kEwaldThreads : kEwaldThreads / 2; }
+inline size_t ewald_lds_bytes(int hmax) {
+    return sizeof(double2) * size_t(hmax + 1 + 2 * (2 * hmax + 1)) * size_t(ewald_threads(hmax));
+}
+
+__global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
+    extern __shared__ double2 ew_lds[];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     if (a.active && !a.active[i]) return;
@@ -996,6 +1025,9 @@ __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
     for (int ix = -R; ix <= R; ++ix)
         for (int iy = -R; iy <= R; ++iy)
             for (int iz = -R; iz <= R; ++iz) {
+                // reload the 44 table values per image (scalar loads, cheap)
+                // rather than keeping them live across the loop
+                asm volatile("" ::: "memory");
                 const bool near = ix >= -1 && ix <= 1 && iy >= -1 && iy <= 1 && iz >= -1 && iz <= 1;
                 const double x = rx - ix, y = ry - iy, z = rz - iz;
                 double g[6];
@@ -1011,56 +1043,63 @@ __global__ void __launch_bounds__(128) k_ewald(EwaldArgs a) {
                 ay -= S * y + g[2] * g2y + g[3] * g3y + g44 * v4y;
                 az -= S * z + g[2] * g2z + g[3] * g3z + g44 * v4z;
             }
-    // k space: walk the wave-vector box in the order of the table rows,
-    // advancing e^{i 2 pi h.r} by one rotation per step (no indexed arrays).
-    const int hm = a.hmax;
-    double s1x, c1x, s1y, c1y, s1z, c1z;
-    sincospi(2.0 * rx, &s1x, &c1x);
-    sincospi(2.0 * ry, &s1y, &c1y);
-    sincospi(2.0 * rz, &s1z, &c1z);
-    // e^{-i 2 pi hm y} and e^{-i 2 pi hm z}
-    double cym = 1.0, sym = 0.0, czm = 1.0, szm = 0.0;
-    for (int m = 0; m < hm; ++m) {
-        double t = cym * c1y + sym * s1y;
-        sym = sym * c1y - cym * s1y;
-        cym = t;
-        t = czm * c1z + szm * s1z;
-        szm = szm * c1z - czm * s1z;
-        czm = t;
+    // k space over the table rows.  Each thread keeps e^{i 2 pi k r_a} for
+    // k = 0..hmax (x) and k = -hmax..hmax (y, z) in LDS (its own column,
+    // built by repeated rotation); a row multiplies one entry per axis.
+    const int hm = a.hmax, T = blockDim.x, tid = threadIdx.x;
+    double2* ex = ew_lds;               // [hm + 1][T]
+    double2* ey = ex + (hm + 1) * T;    // [2 hm + 1][T], index hy + hm
+    double2* ez = ey + (2 * hm + 1) * T;
+    {
+        double s1, c1;
+        sincospi(2.0 * rx, &s1, &c1);
+        double c = 1.0, s = 0.0;
+        ex[tid] = make_double2(1.0, 0.0);
+        for (int k = 1; k <= hm; ++k) {
+            const double t = c * c1 - s * s1;
+            s = s * c1 + c * s1;
+            c = t;
+            ex[k * T + tid] = make_double2(c, s);
+        }
+        sincospi(2.0 * ry, &s1, &c1);
+        c = 1.0;
+        s = 0.0;
+        ey[hm * T + tid] = make_double2(1.0, 0.0);
+        for (int k = 1; k <= hm; ++k) {
+            const double t = c * c1 - s * s1;
+            s = s * c1 + c * s1;
+            c = t;
+            ey[(hm + k) * T + tid] = make_double2(c, s);
+            ey[(hm - k) * T + tid] = make_double2(c, -s);
+        }
+        sincospi(2.0 * rz, &s1, &c1);
+        c = 1.0;
+        s = 0.0;
+        ez[hm * T + tid] = make_double2(1.0, 0.0);
+        for (int k = 1; k <= hm; ++k) {
+            const double t = c * c1 - s * s1;
+            s = s * c1 + c * s1;
+            c = t;
+            ez[(hm + k) * T + tid] = make_double2(c, s);
+            ez[(hm - k) * T + tid] = make_double2(c, -s);
+        }
     }
     const double* tab = a.table + 64;
+    const int64_t* key = reinterpret_cast<const int64_t*>(tab);
     const int nk = int(load_uniform(a.table, 44));
-    int q = 0;
-    double cxh = 1.0, sxh = 0.0;  // e^{i 2 pi hx x}
-    for (int hx = 0; hx <= hm; ++hx) {
-        double cyh = cym, syh = sym;  // e^{i 2 pi hy y}, hy from -hm
-        for (int hy = -hm; hy <= hm; ++hy) {
-            const double cxy = cxh * cyh - sxh * syh, sxy = sxh * cyh + cxh * syh;
-            double czh = czm, szh = szm;
-            for (int hz = -hm; hz <= hm; ++hz) {
-                const int h2 = hx * hx + hy * hy + hz * hz;
-                const bool half = hx > 0 || hy > 0 || (hy == 0 && hz > 0);
-                if (h2 > 0 && h2 <= a.h2max && half && q < nk) {
-                    const int row = 8 * q;
-                    ++q;
-                    const double c = cxy * czh - sxy * szh, s = sxy * czh + cxy * szh;
-                    phi += load_uniform(tab, row + 3) * c + load_uniform(tab, row + 4) * s;
-                    const double f = load_uniform(tab, row + 5) * s + load_uniform(tab, row + 6) * c;
-                    ax += f * double(hx);
-                    ay += f * double(hy);
-                    az += f * double(hz);
-                }
-                const double t = czh * c1z - szh * s1z;
-                szh = szh * c1z + czh * s1z;
-                czh = t;
-            }
-            const double t = cyh * c1y - syh * s1y;
-            syh = syh * c1y + cyh * s1y;
-            cyh = t;
-        }
-        const double t = cxh * c1x - sxh * s1x;
-        sxh = sxh * c1x + cxh * s1x;
-        cxh = t;
+    for (int q = 0; q < nk; ++q) {
+        const int row = 8 * q;
+        const int64_t kk = load_uniform(key, row + 7);  // hx | (hy + hm) << 8 | (hz + hm) << 16
+        const double2 px = ex[int(kk & 0xff) * T + tid];
+        const double2 py = ey[int((kk >> 8) & 0xff) * T + tid];
+        const double2 pz = ez[int((kk >> 16) & 0xff) * T + tid];
+        const double cxy = px.x * py.x - px.y * py.y, sxy = px.y * py.x + px.x * py.y;
+        const double c = cxy * pz.x - sxy * pz.y, s = sxy * pz.x + cxy * pz.y;
+        phi += load_uniform(tab, row + 3) * c + load_uniform(tab, row + 4) * s;
+        const double f = load_uniform(tab, row + 5) * s + load_uniform(tab, row + 6) * c;
+        ax += f * load_uniform(tab, row);
+        ay += f * load_uniform(tab, row + 1);
+        az += f * load_uniform(tab, row + 2);
     }
     phi += load_uniform(a.table, 45);
     // physical units: potential / L, acceleration / L^2
@@ -1505,8 +1544,9 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
                            c->stream, L.r);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {
         hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->stream, L.e);
-        hipLaunchKernelGGL(k_ewald, dim3(unsigned((L.n + 127) / 128)), dim3(128), 0, c->stream,
-                           L.e);
+        const int et = ewald_threads(L.e.hmax);
+        hipLaunchKernelGGL(k_ewald, dim3(unsigned((L.n + et - 1) / et)), dim3(et),
+                           ewald_lds_bytes(L.e.hmax), c->stream, L.e);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE) {
         hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.com,
                            L.mom, L.n_cell, L.sg.ncell, const_cast<double*>(L.sg.cells));

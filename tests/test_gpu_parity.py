@@ -129,6 +129,28 @@ def test_tight_clusters_small_softening(mg_ctx):
     check_parts(mg_ctx, ps, "tight_clusters_16_eps5e-5")
 
 
+@pytest.mark.parametrize("alpha,layers,h2max", [(2.0, 2, 36), (3.0, 1, 4), (2.6, 3, 64), (2.6, 1, 0)])
+def test_ewald_parameters_match_oracle(mg_ctx, alpha, layers, h2max):
+    """The exact correction for other splits, real-space shells and k-space
+    cuts (|h|^2 > 25 runs the 64-thread blocks of the k-space tables,
+    |h|^2 = 0 none at all), on every 5th bucket."""
+    mg, ctx = mg_ctx
+    ps = workloads.perturbed_lattice(16, 0.2, seed=35)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    sel = np.arange(0, tree.n_bucket, 5, dtype=np.int32)
+    idx = np.concatenate([np.arange(tree.cell_first[c], tree.cell_first[c] + tree.cell_count[c])
+                          for c in tree.bucket_cell[sel]])
+    _case(f"Ewald alpha={alpha} layers={layers} h2max={h2max} lattice_16")
+    ew = dict(mode=mg.EWALD_EXACT, alpha=alpha, real_layers=layers, h2max=h2max)
+    ag, pg, _ = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts=mg.PART_EWALD, ewald=ew)
+    ao, po = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, mg.PART_EWALD, buckets=sel,
+                             ewald=dict(alpha=alpha, rmax=layers, h2max=h2max))
+    ea = glob_rel(ag[idx], ao[idx])
+    ep = glob_rel(pg[idx][:, None], po[idx][:, None])
+    print(f"  acc {ea:.3e} pot {ep:.3e}", flush=True)
+    assert ea < TOL_EWALD and ep < TOL_EWALD
+
+
 def test_lattice_periodic_full_size_sampled(mg_ctx):
     check_parts(mg_ctx, workloads.make(2), "lattice_64_full", sample=97)
 
