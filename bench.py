@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=4,
                     help="oracle baseline evaluates every k-th bucket")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep PP + PC kernel variant 0 instead of timing all variants first")
     ap.add_argument("--ewald-study", action="store_true",
                     help="instead of the throughput line: exact vs learned Ewald correction, "
                          "time against force error, on the chosen config (default 4)")
@@ -66,6 +68,9 @@ def main():
 
     if args.ewald_study:
         ewald_study(args)
+        return
+    if args.config == 5:
+        substeps(args)
         return
     cfg = workloads.CONFIGS[args.config]
     ps = workloads.make(args.config)
@@ -95,6 +100,16 @@ def main():
     acc = torch.zeros(3 * ps.n, dtype=torch.float32, device=dev)
     pot = torch.zeros(ps.n, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
+
+    # untimed set-up: pick the PP + PC kernel variant for these lists
+    variants = mg.interact_variants()
+    tuned = {"index": 0, "ms_per_variant": None}
+    if not args.no_autotune:
+        ctx.bind(prob, tensors, ws)
+        v, ms = ctx.autotune(acc, pot, budget_ms=1500.0)
+        tuned = {"index": v, "ms_per_variant": ms}
+    tuned["pp_chunk"], tuned["waves_per_simd"] = variants[tuned["index"]]
+    print(f"[bench] PP + PC kernel variant {tuned}", file=sys.stderr, flush=True)
 
     def step():
         ctx.bind(prob, tensors, ws)
@@ -142,6 +157,7 @@ def main():
             "n": ps.n, "theta": cfg.theta, "bucket": cfg.bucket,
             "parallelism": "single GPU",
         },
+        "interact_variant": tuned,
         "particles_per_s": ps.n / (ms_step * 1e-3),
         "n_pp_interactions": st.n_pp_interactions,
         "n_pc_interactions": st.n_pc_interactions,
@@ -150,7 +166,8 @@ def main():
         "ms_ewald": float(np.mean(ms_e)),
         "roofline": {
             "bound": "alu",
-            "kernel": "k_interact (PP + PC, FP32 vector ALU)",
+            "kernel": f"k_interact<{tuned['pp_chunk']}, {tuned['waves_per_simd']}> "
+                      "(PP + PC, FP32 vector ALU)",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
@@ -164,7 +181,7 @@ def main():
         },
     }
 
-    detail = interact_traffic(cfg.name)
+    detail = interact_traffic(cfg.name, tuned["pp_chunk"], tuned["waves_per_simd"])
     if detail is not None:
         out["roofline"]["traffic"] = detail.pop("bytes_per_launch")
         out["roofline"]["traffic_detail"] = detail
@@ -186,11 +203,11 @@ def interact_source_digest() -> str:
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def interact_traffic(workload: str):
-    """HBM bytes per k_interact launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or
-    None when the summary is missing, for another workload, or taken on
-    different kernel source."""
+def interact_traffic(workload: str, pp_chunk: int, waves: int):
+    """HBM bytes per launch of the k_interact variant (pp_chunk, waves) from
+    the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
+    scaled by a copy of known size), or None when the summary is missing,
+    for another workload or variant, or taken on different kernel source."""
     try:
         with open(COUNTERS) as f:
             rec = json.load(f)
@@ -198,11 +215,14 @@ def interact_traffic(workload: str):
         return None
     if rec.get("workload") != workload or rec.get("source_digest") != interact_source_digest():
         return None
-    return {"bytes_per_launch": rec["traffic_bytes_per_launch"],
-            "fetch_kib_raw": rec["fetch_kib_per_dispatch"],
-            "write_kib_raw": rec["write_kib_per_dispatch"],
+    var = rec.get("variants", {}).get(f"{pp_chunk}x{waves}")
+    if var is None:
+        return None
+    return {"bytes_per_launch": var["traffic_bytes_per_launch"],
+            "fetch_kib_raw": var["fetch_kib_per_dispatch"],
+            "write_kib_raw": var["write_kib_per_dispatch"],
             "fetch_factor": rec["fetch_factor"], "write_factor": rec["write_factor"],
-            "source": os.path.relpath(COUNTERS, ROOT)}
+            "variant": f"{pp_chunk}x{waves}", "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
@@ -243,6 +263,141 @@ def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
         "gpu_rms_rel_acc_err_vs_oracle": err,
         "gpu_rel_pot_err_vs_oracle": perr,
     }
+
+
+def substeps(args):
+    """Individual time steps at one GPU's share: the 512^3 clustered set,
+    forces for the active particles of substeps touching 100 %, 10 % and
+    1 % of them (the largest |a|, from a first full force computation),
+    each timed over K steps of bind + compute with its mask; a sampled-
+    bucket parity check of the full computation against the FP64 oracle.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1609_08621_amd as mg
+    import workloads
+
+    cfg = workloads.CONFIGS[5]
+    t0 = time.perf_counter()
+    ps = workloads.make(5)
+    print(f"[substeps] {cfg.name}: n={ps.n} generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tree = mg.tree_build(ps.pos, ps.mass, ps.box_L, cfg.bucket)
+    print(f"[substeps] tree: {tree.n_cell} cells, {tree.n_bucket} buckets in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    lists = mg.lists_build(tree, cfg.theta, ps.eps)
+    print(f"[substeps] lists: {lists.pp_src.size} PP and {lists.pc_src.size} PC entries in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    pos_t, mass_t = ps.pos[tree.perm], ps.mass[tree.perm]
+    dev = torch.device("cuda", 0)
+    ctx = mg.Context(0)
+    t0 = time.perf_counter()
+    tensors, prob = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, cfg.theta)
+    ws = torch.empty(ctx.workspace_size(prob), dtype=torch.uint8, device=dev)
+    acc = torch.zeros(3 * ps.n, dtype=torch.float32, device=dev)
+    pot = torch.zeros(ps.n, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    print(f"[substeps] upload + workspace ({ws.numel() / 2**30:.1f} GiB) in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    ctx.bind(prob, tensors, ws)
+    tuned = {"index": 0, "ms_per_variant": None}
+    if not args.no_autotune:
+        v, ms = ctx.autotune(acc, pot, budget_ms=3000.0)
+        tuned = {"index": v, "ms_per_variant": ms}
+    tuned["pp_chunk"], tuned["waves_per_simd"] = mg.interact_variants()[tuned["index"]]
+    print(f"[substeps] PP + PC kernel variant {tuned}", file=sys.stderr, flush=True)
+
+    ctx.compute(acc, pot)
+    st = ctx.wait(300.0)
+    a_full = acc.view(3, -1).t().cpu().numpy().astype(np.float64)
+    # sampled-bucket parity of the full computation against the oracle's
+    # own tree and lists (per input particle)
+    a_in = np.empty_like(a_full)
+    a_in[tree.perm] = a_full
+    t0 = time.perf_counter()
+    who, ao = oracle_sample(ps, cfg, 64)
+    rel = np.sum((a_in[who] - ao) ** 2, 1) / np.sum(ao ** 2, 1)
+    parity = {"particles": int(who.size), "rms_rel_acc_err": float(np.sqrt(np.mean(rel))),
+              "max_rel_acc_err": float(np.sqrt(np.max(rel))),
+              "oracle_seconds": time.perf_counter() - t0}
+    print(f"[substeps] full compute {st.ms_total:.1f} ms; sampled parity {parity}",
+          file=sys.stderr, flush=True)
+    amag = np.sqrt(np.sum(a_full ** 2, 1))
+
+    rows = []
+    for frac in (1.0, 0.1, 0.01):
+        if frac < 1.0:
+            mask = torch.from_numpy(workloads.active_by_acceleration(amag, frac)).to(dev)
+        else:
+            mask = None
+
+        def step():
+            ctx.bind(prob, tensors, ws)
+            ctx.set_active(mask)
+            ctx.compute(acc, pot)
+            return ctx.wait(300.0)
+
+        for _ in range(args.warmup if args.warmup < 3 else 2):
+            step()
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 10))
+        ms_k, ms_c = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st = step()
+            ms_k.append(st.ms_interact)
+            ms_c.append(st.ms_total)
+        torch.cuda.synchronize()
+        ms_step = 1e3 * (time.perf_counter() - t0) / steps
+        n_int = st.n_pp_interactions + st.n_pc_interactions
+        row = {"active_fraction": frac, "active_particles": st.n_active_particles,
+               "active_buckets": st.n_active_buckets, "ms_per_step": ms_step,
+               "ms_compute": float(np.mean(ms_c)), "ms_interact_kernel": float(np.mean(ms_k)),
+               "n_pp_interactions": st.n_pp_interactions, "n_pc_interactions": st.n_pc_interactions,
+               "interactions_per_s": n_int / (ms_step * 1e-3),
+               "particles_per_s": st.n_active_particles / (ms_step * 1e-3),
+               "kernel_tflops": (st.n_pp_interactions * FLOP_PP + st.n_pc_interactions * FLOP_PC)
+               / (float(np.mean(ms_k)) * 1e-3) / 1e12}
+        rows.append(row)
+        print(f"[substeps] active {frac:.0%}: {row['active_particles']} particles, step "
+              f"{ms_step:.2f} ms, {row['interactions_per_s']:.3e} interactions/s, "
+              f"{row['particles_per_s']:.3e} particles/s, kernel {row['kernel_tflops']:.1f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    ctx.set_active(None)
+    out = {"metric": "P-P+P-C interactions/s", "value": rows[0]["interactions_per_s"],
+           "unit": "interactions/s", "n_gpus": 1, "steps": steps, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{cfg.name} (n={ps.n}, theta={cfg.theta}, bucket={cfg.bucket}, "
+                                  f"eps={ps.eps:.6g}, Ewald exact: alpha 2.6, 27 images, |h|^2<=10)",
+                      "n": ps.n, "active_fractions": [1.0, 0.1, 0.01]},
+           "interact_variant": tuned, "substeps": rows, "sampled_parity": parity}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def oracle_sample(ps, cfg, nsample):
+    """The FP64 oracle's accelerations for about ``nsample`` sink buckets
+    spread over its own tree (lists walked for those sinks only).  Returns
+    the input indices of their particles and the accelerations."""
+    import dataclasses
+
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    to = oracle.build_tree(ps.pos, ps.mass, ps.box_L, cfg.bucket)
+    print(f"[substeps] oracle tree in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    sel = np.arange(0, to.n_bucket, max(1, to.n_bucket // nsample))
+    sub = dataclasses.replace(to, bucket_cell=np.ascontiguousarray(to.bucket_cell[sel]))
+    lo = oracle.build_lists(sub, cfg.theta, ps.eps)
+    ao, _ = oracle.evaluate(sub, lo, ps.pos[to.perm], ps.mass[to.perm], ps.eps, 7)
+    idx = np.concatenate([np.arange(sub.cell_first[c], sub.cell_first[c] + sub.cell_count[c])
+                          for c in sub.bucket_cell])
+    return to.perm[idx], ao[idx]
 
 
 def ewald_study(args):

@@ -275,6 +275,7 @@ typedef struct {
     double ms_interact;          /* PP + PC kernel of the last compute       */
     double ms_ewald;             /* Ewald kernels of the last compute        */
     int graph_replay;            /* 1: launched from captured HIP graphs     */
+    int interact_variant;        /* PP + PC kernel variant of the last compute */
 } mgrav_stats;
 
 /* Wait for the context's work with a watchdog: polls the completion event
@@ -345,6 +346,37 @@ typedef struct {
  * mgrav_mlp_set_weights.  Blocking. */
 mgrav_status mgrav_mlp_train(mgrav_ctx *ctx, const double *u, const double *psi, int64_t n,
                              const mgrav_train_cfg *cfg, double *loss_host);
+
+/* ---- Autotuning of the PP + PC kernel (persistent launch, Sec. 3.3) ----
+ * The PP + PC kernel is compiled in a few variants: PP source entries
+ * expanded into LDS per fill (`pp_chunk`, 16 particles x 16 B each) and the
+ * occupancy the register allocation aims at (`waves_per_simd`).  Which is
+ * fastest depends on the lists (lengths, PP/PC mix) and on the device.
+ *
+ * mgrav_interact_variants: number of variants (> 0).
+ * mgrav_interact_variant_info: the parameters of one; INVALID_ARG out of
+ *   range.  Either output may be NULL.
+ * mgrav_set_interact_variant: use `variant` from the next compute on
+ *   (default 0).  INVALID_ARG out of range.
+ * mgrav_autotune: on the bound problem, runs the PP + PC parts with every
+ *   variant (the first run of each untimed, then at least two timed runs,
+ *   more while `budget_ms` of wall time lasts), keeps the variant with the
+ *   smallest median kernel time for later computes and stores it in
+ *   `*chosen` (nullable).  `acc`/`pot` (device, as for mgrav_compute) are
+ *   overwritten by the trial runs.  `ms_per_variant` (host, nullable,
+ *   mgrav_interact_variants() entries) receives each median, or -1 when not
+ *   timed.  `cache_path` (nullable) names a text file of lines
+ *   "mgrav-autotune <key> <variant>", the key being device, CU count and the
+ *   list shape (n, buckets, PP and PC entries, images): a matching line is
+ *   used without timing; otherwise the result is appended.  If the file
+ *   cannot be appended to, the chosen variant still applies and the call
+ *   returns INVALID_ARG.  STATE before bind; errors of the trial computes
+ *   are returned as they are.  Blocking. */
+mgrav_status mgrav_interact_variants(int *count);
+mgrav_status mgrav_interact_variant_info(int variant, int *pp_chunk, int *waves_per_simd);
+mgrav_status mgrav_set_interact_variant(mgrav_ctx *ctx, int variant);
+mgrav_status mgrav_autotune(mgrav_ctx *ctx, float *acc, float *pot, const char *cache_path,
+                            double budget_ms, int *chosen, double *ms_per_variant);
 
 #ifdef __cplusplus
 }

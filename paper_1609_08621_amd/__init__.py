@@ -57,7 +57,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_pp_interactions", _I64), ("n_pc_interactions", _I64),
                 ("n_active_buckets", _I64), ("n_active_particles", _I64),
                 ("ms_total", _D), ("ms_interact", _D), ("ms_ewald", _D),
-                ("graph_replay", _I)]
+                ("graph_replay", _I), ("interact_variant", _I)]
 
 
 class TrainConfig(ctypes.Structure):
@@ -118,6 +118,14 @@ def _declare():
     L.mgrav_mlp_backward.argtypes = [_P, _P, _P, _I64, _P]
     L.mgrav_mlp_train.restype = _I
     L.mgrav_mlp_train.argtypes = [_P, _P, _P, _I64, ctypes.POINTER(TrainConfig), _P]
+    L.mgrav_interact_variants.restype = _I
+    L.mgrav_interact_variants.argtypes = [ctypes.POINTER(_I)]
+    L.mgrav_interact_variant_info.restype = _I
+    L.mgrav_interact_variant_info.argtypes = [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]
+    L.mgrav_set_interact_variant.restype = _I
+    L.mgrav_set_interact_variant.argtypes = [_P, _I]
+    L.mgrav_autotune.restype = _I
+    L.mgrav_autotune.argtypes = [_P, _P, _P, ctypes.c_char_p, _D, ctypes.POINTER(_I), _P]
 
 
 _declare()
@@ -130,6 +138,8 @@ EXPORTS = (
     "mgrav_set_active", "mgrav_compute", "mgrav_compute_parts", "mgrav_wait",
     "mgrav_ewald_psi", "mgrav_mlp_workspace_size", "mgrav_mlp_attach", "mgrav_mlp_set_weights",
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
+    "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
+    "mgrav_autotune",
 )
 
 
@@ -196,27 +206,36 @@ def tree_build(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
     n = pos.shape[0]
-    cap = 2 * n + 2
-    perm = np.empty(n, np.int64)
-    cf = np.empty(cap, np.int64)
-    cc = np.empty(cap, np.int32)
-    ch = np.empty(2 * cap, np.int32)
-    com = np.empty(3 * cap)
-    bmax = np.empty(cap)
-    bbox = np.empty(6 * cap)
-    mom = np.empty(32 * cap)
-    bc = np.empty(cap, np.int32)
-    nc = np.zeros(1, np.int64)
-    nb = np.zeros(1, np.int64)
-    _check(_lib.mgrav_tree_build_host(n, _ptr(pos), _ptr(mass), float(box_L), int(bucket), cap,
-                                      _ptr(perm), _ptr(cf), _ptr(cc), _ptr(ch), _ptr(com),
-                                      _ptr(bmax), _ptr(bbox), _ptr(mom), _ptr(bc), _ptr(nc),
-                                      _ptr(nb)))
+    # A tree of buckets of b particles has about 2n/b cells; n/2 covers every
+    # tree with average leaf occupancy of 4 or more.  Degenerate inputs that
+    # need more (the bound is 2n) are built again with the full capacity.
+    for cap in (n // 2 + 64, 2 * n + 2):
+        perm = np.empty(n, np.int64)
+        cf = np.empty(cap, np.int64)
+        cc = np.empty(cap, np.int32)
+        ch = np.empty(2 * cap, np.int32)
+        com = np.empty(3 * cap)
+        bmax = np.empty(cap)
+        bbox = np.empty(6 * cap)
+        mom = np.empty(32 * cap)
+        bc = np.empty(cap, np.int32)
+        nc = np.zeros(1, np.int64)
+        nb = np.zeros(1, np.int64)
+        st = _lib.mgrav_tree_build_host(n, _ptr(pos), _ptr(mass), float(box_L), int(bucket), cap,
+                                        _ptr(perm), _ptr(cf), _ptr(cc), _ptr(ch), _ptr(com),
+                                        _ptr(bmax), _ptr(bbox), _ptr(mom), _ptr(bc), _ptr(nc),
+                                        _ptr(nb))
+        if st == OK:
+            break
+        msg = _lib.mgrav_last_error(None)
+        if st != ERR_INVALID_ARG or b"capacity" not in (msg or b"") or cap >= 2 * n + 2:
+            _check(st)
     c, b = int(nc[0]), int(nb[0])
-    return Tree(perm, cf[:c].copy(), cc[:c].copy(), ch[:2 * c].reshape(c, 2).copy(),
-                com[:3 * c].reshape(c, 3).copy(), bmax[:c].copy(),
-                bbox[:6 * c].reshape(c, 6).copy(), mom[:32 * c].reshape(c, 32).copy(),
-                bc[:b].copy(), float(box_L))
+    # views of the first c cells (no copy: at 512^3 the moment array alone
+    # is several GB)
+    return Tree(perm, cf[:c], cc[:c], ch[:2 * c].reshape(c, 2), com[:3 * c].reshape(c, 3),
+                bmax[:c], bbox[:6 * c].reshape(c, 6), mom[:32 * c].reshape(c, 32), bc[:b],
+                float(box_L))
 
 
 def lists_build(tree: Tree, theta: float, eps: float, n_images: Optional[int] = None) -> Lists:
@@ -242,6 +261,19 @@ def lists_build(tree: Tree, theta: float, eps: float, n_images: Optional[int] = 
 # --------------------------------------------------------------------------
 # Device side
 # --------------------------------------------------------------------------
+def interact_variants():
+    """[(pp_chunk, waves_per_simd), ...] of the compiled PP + PC kernel
+    variants, by index."""
+    n = _I(0)
+    _check(_lib.mgrav_interact_variants(ctypes.byref(n)))
+    out = []
+    for v in range(n.value):
+        ch, wv = _I(0), _I(0)
+        _check(_lib.mgrav_interact_variant_info(v, ctypes.byref(ch), ctypes.byref(wv)))
+        out.append((ch.value, wv.value))
+    return out
+
+
 class Context:
     """One mgrav context on a device and a (torch) HIP stream."""
 
@@ -336,6 +368,22 @@ class Context:
         cfg = EwaldConfig(int(mode), float(alpha), int(real_layers), int(h2max), int(order),
                           int(top_cells))
         _check(_lib.mgrav_set_ewald(self._h, ctypes.byref(cfg)), self._h)
+
+    def set_interact_variant(self, variant: int):
+        _check(_lib.mgrav_set_interact_variant(self._h, int(variant)), self._h)
+
+    def autotune(self, acc, pot, cache_path: Optional[str] = None, budget_ms: float = 2000.0):
+        """Time every PP + PC kernel variant on the bound problem and keep the
+        fastest.  Returns (variant, [median ms per variant, -1 if untimed])."""
+        torch = self._torch
+        self.stream.wait_stream(torch.cuda.current_stream(torch.device("cuda", self.device)))
+        nv = len(interact_variants())
+        ms = (_D * nv)()
+        chosen = _I(-1)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(_lib.mgrav_autotune(self._h, _P(acc.data_ptr()), _P(pot.data_ptr()), path,
+                                   float(budget_ms), ctypes.byref(chosen), ms), self._h)
+        return chosen.value, list(ms)
 
     def set_active(self, active_dev=None):
         self._keep["active"] = active_dev

@@ -19,9 +19,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <thread>
+#include <utility>
 
 #include "../../include/mgrav.h"
 #include "internal.h"
@@ -31,17 +33,12 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kBucket = MGRAV_MAX_BUCKET;  // 16 sinks per work item
 constexpr int kRec = 44;                   // floats per staged cell record
-// Tuning knobs (compile time): PP entries expanded into LDS per fill, and
-// the occupancy target of the PP + PC kernel (waves per SIMD).
-#ifndef MGRAV_PP_CHUNK
-#define MGRAV_PP_CHUNK 48
-#endif
-#ifndef MGRAV_INTERACT_WAVES
-#define MGRAV_INTERACT_WAVES 3
-#endif
-constexpr int kChunk = MGRAV_PP_CHUNK;     // PP entries expanded per LDS fill
-constexpr int kLdsSrc = kChunk * kBucket;  // source particles per fill
-static_assert(kChunk >= 1 && kChunk <= kWave, "a PP fill uses one entry per lane");
+// Variants of the PP + PC kernel that the autotuner chooses from: PP
+// entries expanded into LDS per fill (LDS = 16 x 16 B per entry) and the
+// occupancy target (waves per SIMD) the register allocation aims at.
+constexpr int kNumVariants = 4;
+constexpr int kVariantChunk[kNumVariants] = {48, 32, 64, 32};
+constexpr int kVariantWaves[kNumVariants] = {3, 3, 2, 2};
 constexpr int kMaxH2 = 64;                 // largest k-space cut-off |h|^2
 constexpr int kMaxHalfK = 1054;            // half-space wave vectors with |h|^2 <= 64
 constexpr int kErrTree = 1, kErrList = 2, kErrParticle = 4;
@@ -644,8 +641,11 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 // PC cells' coefficient records in vector registers.  Each lane keeps
 // 16 x 4 partial sums; a transposing butterfly reduction leaves lane l
 // with component l&3 of sink l>>2.
+template <int kChunk, int kWaves>
 __global__ void __launch_bounds__(kWave)
-    __attribute__((amdgpu_waves_per_eu(MGRAV_INTERACT_WAVES, 8))) k_interact(RunArgs a) {
+    __attribute__((amdgpu_waves_per_eu(kWaves, 8))) k_interact(RunArgs a) {
+    static_assert(kChunk >= 1 && kChunk <= kWave, "a PP fill uses one entry per lane");
+    constexpr int kLdsSrc = kChunk * kBucket;  // source particles per fill
     __shared__ float4 lds[kLdsSrc];
     __shared__ int4 etab[kChunk];    // per PP entry of a fill: LDS base, count, first
     __shared__ float4 edel[kChunk];  // per PP entry of a fill: source-sink offset
@@ -795,6 +795,37 @@ __global__ void __launch_bounds__(kWave)
             }
         }
         item = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
+    }
+}
+
+// The compiled variants of the PP + PC kernel, by index.
+const void* interact_kernel(int v) {
+    switch (v) {
+        case 1: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[1], kVariantWaves[1]>);
+        case 2: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[2], kVariantWaves[2]>);
+        case 3: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[3], kVariantWaves[3]>);
+        default: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[0], kVariantWaves[0]>);
+    }
+}
+
+void launch_interact(int v, dim3 grid, hipStream_t stream, const RunArgs& r) {
+    switch (v) {
+        case 1:
+            hipLaunchKernelGGL((k_interact<kVariantChunk[1], kVariantWaves[1]>), grid, dim3(kWave),
+                               0, stream, r);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_interact<kVariantChunk[2], kVariantWaves[2]>), grid, dim3(kWave),
+                               0, stream, r);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_interact<kVariantChunk[3], kVariantWaves[3]>), grid, dim3(kWave),
+                               0, stream, r);
+            break;
+        default:
+            hipLaunchKernelGGL((k_interact<kVariantChunk[0], kVariantWaves[0]>), grid, dim3(kWave),
+                               0, stream, r);
+            break;
     }
 }
 
@@ -1160,8 +1191,10 @@ struct mgrav_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int n_cu = 0;
-    int interact_blocks = 0;
+    std::string arch;  // gcnArchName, part of the autotuning cache key
+    int interact_blocks[kNumVariants] = {};  // persistent grid per variant
     int occupancy_status = 0;
+    int variant = 0;  // PP + PC kernel variant in use (mgrav_autotune)
     std::string err;
     bool bound = false;
     bool failed = false;
@@ -1192,7 +1225,7 @@ struct LaunchSet {
     const double* mom;
     const double* com;
     int64_t n, n_bucket, n_cell;
-    int use_mask, tree, ewald, interact_blocks, surrogate_blocks;
+    int use_mask, tree, ewald, variant, interact_blocks, surrogate_blocks;
 };
 
 namespace {
@@ -1331,14 +1364,17 @@ mgrav_status mgrav_create(int device, void* hip_stream, mgrav_ctx** out) {
         return hip_fail(nullptr, e, "hipGetDeviceProperties");
     }
     c->n_cu = prop.multiProcessorCount;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_interact, kWave, 0);
-    if (e != hipSuccess || per_cu < 1) {
-        (void)hipGetLastError();  // tolerated: fall back to a fixed occupancy
-        per_cu = 8;
+    c->arch = prop.gcnArchName;
+    for (int v = 0; v < kNumVariants; ++v) {
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, interact_kernel(v), kWave, 0);
+        if (e != hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();  // tolerated: fall back to a fixed occupancy
+            per_cu = 8;
+            c->occupancy_status = int(e);
+        }
+        c->interact_blocks[v] = per_cu * c->n_cu;
     }
-    c->occupancy_status = int(e);
-    c->interact_blocks = per_cu * c->n_cu;
     if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_end) != hipSuccess ||
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
         hipEventCreate(&c->ev_e1) != hipSuccess ||
@@ -1477,8 +1513,10 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     L->use_mask = c->active ? 1 : 0;
     L->tree = (parts & (MGRAV_PART_PP | MGRAV_PART_PC)) != 0;
     L->ewald = (parts & MGRAV_PART_EWALD) ? c->ewald.mode : MGRAV_EWALD_NONE;
-    L->interact_blocks =
-        int(p.n_bucket < c->interact_blocks ? p.n_bucket : c->interact_blocks);
+    L->variant = c->variant;
+    L->interact_blocks = int(p.n_bucket < c->interact_blocks[c->variant]
+                                 ? p.n_bucket
+                                 : c->interact_blocks[c->variant]);
     if (L->ewald == MGRAV_EWALD_SURROGATE) {
         SurrogateArgs& g = L->sg;
         const MlpLayoutT& ml = c->mlp.lay;
@@ -1540,8 +1578,7 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         hipLaunchKernelGGL(k_order_scatter, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256),
                            0, c->stream, L.r);
     } else if (phase == 1 && L.tree) {
-        hipLaunchKernelGGL(k_interact, dim3(unsigned(L.interact_blocks)), dim3(kWave), 0,
-                           c->stream, L.r);
+        launch_interact(L.variant, dim3(unsigned(L.interact_blocks)), c->stream, L.r);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {
         hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->stream, L.e);
         const int et = ewald_threads(L.e.hmax);
@@ -1672,6 +1709,7 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
             if (hipEventElapsedTime(&ms, c->ev_k1, c->ev_e1) == hipSuccess)
                 stats->ms_ewald = ms;
             stats->graph_replay = c->gexec[0] != nullptr ? 1 : 0;
+            stats->interact_variant = c->g_set ? c->g_set->variant : c->variant;
         }
     }
     const int err = c->host_ctl->err;
@@ -1679,6 +1717,107 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
     if (err & kErrList) return fail(c, MGRAV_ERR_BAD_LIST, "list check failed on the device");
     if (err & kErrParticle)
         return fail(c, MGRAV_ERR_INVALID_ARG, "non-finite position or non-positive mass");
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_interact_variants(int* count) {
+    if (!count) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "count is NULL");
+    *count = kNumVariants;
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_interact_variant_info(int variant, int* pp_chunk, int* waves_per_simd) {
+    if (variant < 0 || variant >= kNumVariants)
+        return fail(nullptr, MGRAV_ERR_INVALID_ARG, "variant out of range");
+    if (pp_chunk) *pp_chunk = kVariantChunk[variant];
+    if (waves_per_simd) *waves_per_simd = kVariantWaves[variant];
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_set_interact_variant(mgrav_ctx* c, int variant) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (variant < 0 || variant >= kNumVariants)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "variant out of range");
+    c->variant = variant;
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* cache_path,
+                            double budget_ms, int* chosen, double* ms_per_variant) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (!c->bound) return fail(c, MGRAV_ERR_STATE, "autotune before bind");
+    if (!acc || !pot) return fail(c, MGRAV_ERR_INVALID_ARG, "null output");
+    if (!(budget_ms >= 0.0)) return fail(c, MGRAV_ERR_INVALID_ARG, "budget_ms must be >= 0");
+    if (ms_per_variant)
+        for (int v = 0; v < kNumVariants; ++v) ms_per_variant[v] = -1.0;
+    // cache key: device, CU count and the shape of the bound lists
+    char key[256];
+    std::snprintf(key, sizeof(key), "%s/cu%d/n%lld/b%lld/pp%lld/pc%lld/img%d",
+                  c->arch.c_str(), c->n_cu, (long long)c->prob.n, (long long)c->prob.n_bucket,
+                  (long long)c->prob.n_pp, (long long)c->prob.n_pc, c->prob.n_images);
+    if (cache_path) {
+        int hit = -1;
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            // lines "mgrav-autotune <key> <variant>"; other lines are
+            // ignored, the last match wins
+            char line[512], k[256];
+            int v = -1;
+            while (std::fgets(line, sizeof(line), f)) {
+                if (std::sscanf(line, "mgrav-autotune %255s %d", k, &v) == 2 &&
+                    std::strcmp(k, key) == 0 && v >= 0 && v < kNumVariants)
+                    hit = v;
+            }
+            std::fclose(f);
+        }
+        if (hit >= 0) {
+            c->variant = hit;
+            if (chosen) *chosen = hit;
+            return MGRAV_OK;
+        }
+    }
+    const int saved = c->variant;
+    const auto t0 = std::chrono::steady_clock::now();
+    double best = 0.0;
+    int best_v = saved;
+    for (int v = 0; v < kNumVariants; ++v) {
+        c->variant = v;
+        double ms[8];
+        int got = 0;
+        // the first run of a variant captures its graph and is not timed;
+        // at least two timed runs each, more while the budget lasts
+        for (int rep = 0; rep < 9; ++rep) {
+            mgrav_status st = mgrav_compute_parts(c, MGRAV_PART_PP | MGRAV_PART_PC, acc, pot);
+            mgrav_stats stats{};
+            if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, &stats);
+            if (st != MGRAV_OK) {
+                c->variant = saved;
+                return st;
+            }
+            if (rep > 0) ms[got++] = stats.ms_interact;
+            const double spent =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                    .count();
+            if (got >= 2 && spent > budget_ms * (v + 1) / kNumVariants) break;
+        }
+        for (int i = 1; i < got; ++i)  // median of the timed runs
+            for (int j = i; j > 0 && ms[j] < ms[j - 1]; --j) std::swap(ms[j], ms[j - 1]);
+        const double med = got % 2 ? ms[got / 2] : 0.5 * (ms[got / 2 - 1] + ms[got / 2]);
+        if (ms_per_variant) ms_per_variant[v] = med;
+        if (v == 0 || med < best) {
+            best = med;
+            best_v = v;
+        }
+    }
+    c->variant = best_v;
+    if (chosen) *chosen = best_v;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(c, MGRAV_ERR_INVALID_ARG, "cannot append to cache_path (variant applied)");
+        std::fprintf(f, "mgrav-autotune %s %d\n", key, best_v);
+        std::fclose(f);
+    }
     return MGRAV_OK;
 }
 

@@ -151,6 +151,51 @@ def test_ewald_parameters_match_oracle(mg_ctx, alpha, layers, h2max):
     assert ea < TOL_EWALD and ep < TOL_EWALD
 
 
+def test_every_interact_variant_matches_oracle(mg_ctx):
+    """Each compiled variant of the PP + PC kernel (PP chunk x occupancy)
+    against the oracle on the same clustered problem."""
+    mg, ctx = mg_ctx
+    ps = workloads.make(3, scale_n1d=20)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    ao, _ = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, mg.PART_PP | mg.PART_PC)
+    try:
+        for v, (chunk, waves) in enumerate(mg.interact_variants()):
+            _case(f"interact variant {v} (pp_chunk {chunk}, waves {waves}) clustered_20")
+            ctx.set_interact_variant(v)
+            ag, _, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts=mg.PART_PP | mg.PART_PC,
+                            ewald=dict(mode=mg.EWALD_NONE))
+            err = rel_rms(ag, ao)
+            print(f"  rel_rms {err:.3e} kernel {st.ms_interact:.3f} ms", flush=True)
+            assert st.interact_variant == v
+            assert err < TOL_PART
+    finally:
+        ctx.set_interact_variant(0)
+
+
+def test_autotune_chooses_and_caches(mg_ctx, tmp_path):
+    mg, ctx = mg_ctx
+    ps = workloads.make(2, scale_n1d=24)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+    ctx.bind(p, tensors)
+    acc, pot = ctx.outputs()
+    cache = str(tmp_path / "tune.txt")
+    _case("autotune lattice_24 (timing, then cache hit)")
+    try:
+        v, ms = ctx.autotune(acc, pot, cache_path=cache, budget_ms=500.0)
+        print(f"  chose {v}, ms {['%.3f' % m for m in ms]}", flush=True)
+        assert 0 <= v < len(ms) and all(m > 0 for m in ms)
+        assert v == int(np.argmin(ms))
+        lines = open(cache).read().split("\n")
+        assert lines[0].startswith("mgrav-autotune ") and lines[0].endswith(f" {v}")
+        v2, ms2 = ctx.autotune(acc, pot, cache_path=cache, budget_ms=500.0)
+        assert v2 == v and all(m == -1.0 for m in ms2)
+        ctx.compute(acc, pot)
+        assert ctx.wait(60).interact_variant == v
+    finally:
+        ctx.set_interact_variant(0)
+
+
 def test_lattice_periodic_full_size_sampled(mg_ctx):
     check_parts(mg_ctx, workloads.make(2), "lattice_64_full", sample=97)
 
