@@ -147,27 +147,30 @@ def build_tree(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
     n = pos.shape[0]
-    cap = 2 * n + 2
-    perm = np.empty(n, np.int64)
-    cf = np.empty(cap, np.int64)
-    cc = np.empty(cap, np.int32)
-    ch = np.empty(2 * cap, np.int32)
-    com = np.empty(3 * cap)
-    bmax = np.empty(cap)
-    bbox = np.empty(6 * cap)
-    mom = np.empty(32 * cap)
-    bc = np.empty(cap, np.int32)
-    nb = np.zeros(1, np.int64)
-    nc = lib().orc_tree_build(n, _p(pos), _p(mass), float(box_L), int(bucket), cap, _p(perm),
-                              _p(cf), _p(cc), _p(ch), _p(com), _p(bmax), _p(bbox), _p(mom),
-                              _p(bc), _p(nb))
+    # room for n/2 cells first (trees of buckets hold about 2n/bucket), the
+    # 2n bound only if the builder reports that n/2 is not enough
+    for cap in (n // 2 + 64, 2 * n + 2):
+        perm = np.empty(n, np.int64)
+        cf = np.empty(cap, np.int64)
+        cc = np.empty(cap, np.int32)
+        ch = np.empty(2 * cap, np.int32)
+        com = np.empty(3 * cap)
+        bmax = np.empty(cap)
+        bbox = np.empty(6 * cap)
+        mom = np.empty(32 * cap)
+        bc = np.empty(cap, np.int32)
+        nb = np.zeros(1, np.int64)
+        nc = lib().orc_tree_build(n, _p(pos), _p(mass), float(box_L), int(bucket), cap,
+                                  _p(perm), _p(cf), _p(cc), _p(ch), _p(com), _p(bmax),
+                                  _p(bbox), _p(mom), _p(bc), _p(nb))
+        if nc >= 0:
+            break
     if nc < 0:
         raise RuntimeError("oracle tree build failed")
     nb = int(nb[0])
-    return Tree(perm, cf[:nc].copy(), cc[:nc].copy(), ch[:2 * nc].reshape(nc, 2).copy(),
-                com[:3 * nc].reshape(nc, 3).copy(), bmax[:nc].copy(),
-                bbox[:6 * nc].reshape(nc, 6).copy(), mom[:32 * nc].reshape(nc, 32).copy(),
-                bc[:nb].copy(), float(box_L), int(bucket))
+    return Tree(perm, cf[:nc], cc[:nc], ch[:2 * nc].reshape(nc, 2), com[:3 * nc].reshape(nc, 3),
+                bmax[:nc], bbox[:6 * nc].reshape(nc, 6), mom[:32 * nc].reshape(nc, 32), bc[:nb],
+                float(box_L), int(bucket))
 
 
 def build_lists(tree: Tree, theta: float, eps: float, n_images: Optional[int] = None) -> Lists:
