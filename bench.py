@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--cpu-stride", type=int, default=4,
+    ap.add_argument("--cpu-stride", type=int, default=1,
                     help="oracle baseline evaluates every k-th bucket")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -108,7 +108,7 @@ def main():
         ctx.bind(prob, tensors, ws)
         v, ms = ctx.autotune(acc, pot, budget_ms=1500.0)
         tuned = {"index": v, "ms_per_variant": ms}
-    tuned["pp_chunk"], tuned["waves_per_simd"] = variants[tuned["index"]]
+    tuned["pp_chunk"], tuned["waves_per_simd"], tuned["pc_prefetch"] = variants[tuned["index"]]
     print(f"[bench] PP + PC kernel variant {tuned}", file=sys.stderr, flush=True)
 
     def step():
@@ -166,7 +166,8 @@ def main():
         "ms_ewald": float(np.mean(ms_e)),
         "roofline": {
             "bound": "alu",
-            "kernel": f"k_interact<{tuned['pp_chunk']}, {tuned['waves_per_simd']}> "
+            "kernel": f"k_interact<{tuned['pp_chunk']}, {tuned['waves_per_simd']}, "
+                      f"{'true' if tuned['pc_prefetch'] else 'false'}> "
                       "(PP + PC, FP32 vector ALU)",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
@@ -181,7 +182,8 @@ def main():
         },
     }
 
-    detail = interact_traffic(cfg.name, tuned["pp_chunk"], tuned["waves_per_simd"])
+    detail = interact_traffic(cfg.name, tuned["pp_chunk"], tuned["waves_per_simd"],
+                              tuned["pc_prefetch"])
     if detail is not None:
         out["roofline"]["traffic"] = detail.pop("bytes_per_launch")
         out["roofline"]["traffic_detail"] = detail
@@ -203,8 +205,9 @@ def interact_source_digest() -> str:
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def interact_traffic(workload: str, pp_chunk: int, waves: int):
-    """HBM bytes per launch of the k_interact variant (pp_chunk, waves) from
+def interact_traffic(workload: str, pp_chunk: int, waves: int, prefetch: int):
+    """HBM bytes per launch of the k_interact variant (pp_chunk, waves,
+    prefetch) from
     the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
     scaled by a copy of known size), or None when the summary is missing,
     for another workload or variant, or taken on different kernel source."""
@@ -215,14 +218,15 @@ def interact_traffic(workload: str, pp_chunk: int, waves: int):
         return None
     if rec.get("workload") != workload or rec.get("source_digest") != interact_source_digest():
         return None
-    var = rec.get("variants", {}).get(f"{pp_chunk}x{waves}")
+    key = f"{pp_chunk}x{waves}x{'true' if prefetch else 'false'}"
+    var = rec.get("variants", {}).get(key)
     if var is None:
         return None
     return {"bytes_per_launch": var["traffic_bytes_per_launch"],
             "fetch_kib_raw": var["fetch_kib_per_dispatch"],
             "write_kib_raw": var["write_kib_per_dispatch"],
             "fetch_factor": rec["fetch_factor"], "write_factor": rec["write_factor"],
-            "variant": f"{pp_chunk}x{waves}", "source": os.path.relpath(COUNTERS, ROOT)}
+            "variant": key, "source": os.path.relpath(COUNTERS, ROOT)}
 
 
 def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
@@ -256,9 +260,11 @@ def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
         "unit": "interactions/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"every {args.cpu_stride}th sink bucket ({sel.size} of {to.n_bucket}, "
-                  f"{idx.size} particles, {n_int} PP+PC interactions plus their Ewald "
-                  f"corrections) in {dt:.1f} s",
+        "sample": (("every sink bucket" if args.cpu_stride == 1 else
+                    f"every {args.cpu_stride}th sink bucket") +
+                   f" ({sel.size} of {to.n_bucket}, {idx.size} particles, {n_int} PP+PC "
+                   f"interactions plus their Ewald corrections, one step of the workload) "
+                   f"in {dt:.1f} s"),
         "seconds": dt,
         "gpu_rms_rel_acc_err_vs_oracle": err,
         "gpu_rel_pot_err_vs_oracle": perr,
@@ -307,7 +313,8 @@ def substeps(args):
     if not args.no_autotune:
         v, ms = ctx.autotune(acc, pot, budget_ms=3000.0)
         tuned = {"index": v, "ms_per_variant": ms}
-    tuned["pp_chunk"], tuned["waves_per_simd"] = mg.interact_variants()[tuned["index"]]
+    tuned["pp_chunk"], tuned["waves_per_simd"], tuned["pc_prefetch"] = \
+        mg.interact_variants()[tuned["index"]]
     print(f"[substeps] PP + PC kernel variant {tuned}", file=sys.stderr, flush=True)
 
     ctx.compute(acc, pot)

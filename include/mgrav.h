@@ -181,8 +181,10 @@ typedef struct {
 /* Device workspace the caller must provide to mgrav_bind for `p`. */
 mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
 
-/* Bind a problem: checks the scalar arguments on the host, then enqueues
- * on the stream the staging kernels that
+/* Bind a problem: checks the scalar arguments on the host and arranges
+ * for the staging kernels to run first in the next mgrav_compute (inside
+ * its first captured graph; a mgrav_wait that comes first runs them
+ * itself).  The staging kernels
  *   (1) store every particle as float offsets from its bucket's centre
  *       (the centre itself stays in double precision) and its mass,
  *   (2) convert each cell's moments into the float coefficients of the
@@ -194,7 +196,9 @@ mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
  * neutralised (never dereferenced) and reported by the next mgrav_wait as
  * BAD_TREE or BAD_LIST.  `workspace` is a device buffer of at least
  * mgrav_workspace_size() bytes, 256-byte aligned, owned by the caller and
- * borrowed until the next bind or destroy.  Re-binding is allowed at any
+ * borrowed until the next bind or destroy.  The device reads the positions
+ * and lists when the staging runs, so binding once per step with moved
+ * positions (same buffers) re-stages them.  Re-binding is allowed at any
  * time after the previous work on the stream. */
 mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace, size_t bytes);
 
@@ -349,13 +353,15 @@ mgrav_status mgrav_mlp_train(mgrav_ctx *ctx, const double *u, const double *psi,
 
 /* ---- Autotuning of the PP + PC kernel (persistent launch, Sec. 3.3) ----
  * The PP + PC kernel is compiled in a few variants: PP source entries
- * expanded into LDS per fill (`pp_chunk`, 16 particles x 16 B each) and the
- * occupancy the register allocation aims at (`waves_per_simd`).  Which is
+ * expanded into LDS per fill (`pp_chunk`, 16 particles x 16 B each), the
+ * occupancy the register allocation aims at (`waves_per_simd`) and whether
+ * the next PC chunk's cell records are loaded while the current one is
+ * evaluated (`pc_prefetch`, 2-wave variants only).  Which is
  * fastest depends on the lists (lengths, PP/PC mix) and on the device.
  *
  * mgrav_interact_variants: number of variants (> 0).
  * mgrav_interact_variant_info: the parameters of one; INVALID_ARG out of
- *   range.  Either output may be NULL.
+ *   range.  Any output may be NULL.
  * mgrav_set_interact_variant: use `variant` from the next compute on
  *   (default 0).  INVALID_ARG out of range.
  * mgrav_autotune: on the bound problem, runs the PP + PC parts with every
@@ -373,7 +379,8 @@ mgrav_status mgrav_mlp_train(mgrav_ctx *ctx, const double *u, const double *psi,
  *   returns INVALID_ARG.  STATE before bind; errors of the trial computes
  *   are returned as they are.  Blocking. */
 mgrav_status mgrav_interact_variants(int *count);
-mgrav_status mgrav_interact_variant_info(int variant, int *pp_chunk, int *waves_per_simd);
+mgrav_status mgrav_interact_variant_info(int variant, int *pp_chunk, int *waves_per_simd,
+                                         int *pc_prefetch);
 mgrav_status mgrav_set_interact_variant(mgrav_ctx *ctx, int variant);
 mgrav_status mgrav_autotune(mgrav_ctx *ctx, float *acc, float *pot, const char *cache_path,
                             double budget_ms, int *chosen, double *ms_per_variant);

@@ -121,7 +121,8 @@ def _declare():
     L.mgrav_interact_variants.restype = _I
     L.mgrav_interact_variants.argtypes = [ctypes.POINTER(_I)]
     L.mgrav_interact_variant_info.restype = _I
-    L.mgrav_interact_variant_info.argtypes = [_I, ctypes.POINTER(_I), ctypes.POINTER(_I)]
+    L.mgrav_interact_variant_info.argtypes = [_I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                              ctypes.POINTER(_I)]
     L.mgrav_set_interact_variant.restype = _I
     L.mgrav_set_interact_variant.argtypes = [_P, _I]
     L.mgrav_autotune.restype = _I
@@ -262,15 +263,16 @@ def lists_build(tree: Tree, theta: float, eps: float, n_images: Optional[int] = 
 # Device side
 # --------------------------------------------------------------------------
 def interact_variants():
-    """[(pp_chunk, waves_per_simd), ...] of the compiled PP + PC kernel
-    variants, by index."""
+    """[(pp_chunk, waves_per_simd, pc_prefetch), ...] of the compiled PP + PC
+    kernel variants, by index."""
     n = _I(0)
     _check(_lib.mgrav_interact_variants(ctypes.byref(n)))
     out = []
     for v in range(n.value):
-        ch, wv = _I(0), _I(0)
-        _check(_lib.mgrav_interact_variant_info(v, ctypes.byref(ch), ctypes.byref(wv)))
-        out.append((ch.value, wv.value))
+        ch, wv, pf = _I(0), _I(0), _I(0)
+        _check(_lib.mgrav_interact_variant_info(v, ctypes.byref(ch), ctypes.byref(wv),
+                                                ctypes.byref(pf)))
+        out.append((ch.value, wv.value, pf.value))
     return out
 
 

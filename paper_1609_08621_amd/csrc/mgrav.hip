@@ -36,9 +36,11 @@ constexpr int kRec = 44;                   // floats per staged cell record
 // Variants of the PP + PC kernel that the autotuner chooses from: PP
 // entries expanded into LDS per fill (LDS = 16 x 16 B per entry) and the
 // occupancy target (waves per SIMD) the register allocation aims at.
-constexpr int kNumVariants = 4;
-constexpr int kVariantChunk[kNumVariants] = {48, 32, 64, 32};
-constexpr int kVariantWaves[kNumVariants] = {3, 3, 2, 2};
+// The 2-wave variants can also prefetch the next PC chunk's records.
+constexpr int kNumVariants = 6;
+constexpr int kVariantChunk[kNumVariants] = {48, 32, 64, 32, 32, 64};
+constexpr int kVariantWaves[kNumVariants] = {3, 3, 2, 2, 2, 2};
+constexpr bool kVariantPrefetch[kNumVariants] = {false, false, false, false, true, true};
 constexpr int kMaxH2 = 64;                 // largest k-space cut-off |h|^2
 constexpr int kMaxHalfK = 1054;            // half-space wave vectors with |h|^2 <= 64
 constexpr int kErrTree = 1, kErrList = 2, kErrParticle = 4;
@@ -138,6 +140,15 @@ struct StageArgs {
     float4* ppent;
     float4* pcent;
 };
+
+// The control block (counters, error bits) into pinned host memory: the
+// last kernel of a compute; the host reads it after the completion event.
+__global__ void k_copy_control(const Control* ctl, Control* host) {
+    const int* src = reinterpret_cast<const int*>(ctl);
+    int* dst = reinterpret_cast<int*>(host);
+    for (int i = threadIdx.x; i < int(sizeof(Control) / sizeof(int)); i += blockDim.x)
+        dst[i] = src[i];
+}
 
 __global__ void k_init_control(Control* ctl) {
     if (threadIdx.x == 0) {
@@ -641,7 +652,7 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 // PC cells' coefficient records in vector registers.  Each lane keeps
 // 16 x 4 partial sums; a transposing butterfly reduction leaves lane l
 // with component l&3 of sink l>>2.
-template <int kChunk, int kWaves>
+template <int kChunk, int kWaves, bool kPrefetch>
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(kWaves, 8))) k_interact(RunArgs a) {
     static_assert(kChunk >= 1 && kChunk <= kWave, "a PP fill uses one entry per lane");
@@ -749,14 +760,33 @@ __global__ void __launch_bounds__(kWave)
         }
         if (a.parts & MGRAV_PART_PC) {
             const int64_t f0 = wk.pc0, f1 = wk.pc1;
-            for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
-                float r[kRec], cx, cy, cz;
-                load_pc(a, c0 + lane, f1, r, cx, cy, cz);
-                const float t = r[kRec - 1];
-                const float eps2t = a.eps2 * t * t;
+            if constexpr (kPrefetch) {
+                // the next chunk's records load while this one computes
+                // (44 more registers: the 2-wave variants have them)
+                float rn[kRec], nx, ny, nz;
+                load_pc(a, f0 + lane, f1, rn, nx, ny, nz);
+                for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
+                    float r[kRec];
 #pragma unroll
-                for (int i = 0; i < kBucket; ++i)
-                    if (i < nsink) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                    for (int i = 0; i < kRec; ++i) r[i] = rn[i];
+                    const float cx = nx, cy = ny, cz = nz;
+                    if (c0 + kWave < f1) load_pc(a, c0 + kWave + lane, f1, rn, nx, ny, nz);
+                    const float t = r[kRec - 1];
+                    const float eps2t = a.eps2 * t * t;
+#pragma unroll
+                    for (int i = 0; i < kBucket; ++i)
+                        if (i < nsink) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                }
+            } else {
+                for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
+                    float r[kRec], cx, cy, cz;
+                    load_pc(a, c0 + lane, f1, r, cx, cy, cz);
+                    const float t = r[kRec - 1];
+                    const float eps2t = a.eps2 * t * t;
+#pragma unroll
+                    for (int i = 0; i < kBucket; ++i)
+                        if (i < nsink) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                }
             }
         }
 
@@ -799,35 +829,31 @@ __global__ void __launch_bounds__(kWave)
 }
 
 // The compiled variants of the PP + PC kernel, by index.
+#define MGRAV_VARIANT(V) k_interact<kVariantChunk[V], kVariantWaves[V], kVariantPrefetch[V]>
+
 const void* interact_kernel(int v) {
     switch (v) {
-        case 1: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[1], kVariantWaves[1]>);
-        case 2: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[2], kVariantWaves[2]>);
-        case 3: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[3], kVariantWaves[3]>);
-        default: return reinterpret_cast<const void*>(&k_interact<kVariantChunk[0], kVariantWaves[0]>);
+        case 1: return reinterpret_cast<const void*>(&MGRAV_VARIANT(1));
+        case 2: return reinterpret_cast<const void*>(&MGRAV_VARIANT(2));
+        case 3: return reinterpret_cast<const void*>(&MGRAV_VARIANT(3));
+        case 4: return reinterpret_cast<const void*>(&MGRAV_VARIANT(4));
+        case 5: return reinterpret_cast<const void*>(&MGRAV_VARIANT(5));
+        default: return reinterpret_cast<const void*>(&MGRAV_VARIANT(0));
     }
 }
 
 void launch_interact(int v, dim3 grid, hipStream_t stream, const RunArgs& r) {
     switch (v) {
-        case 1:
-            hipLaunchKernelGGL((k_interact<kVariantChunk[1], kVariantWaves[1]>), grid, dim3(kWave),
-                               0, stream, r);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_interact<kVariantChunk[2], kVariantWaves[2]>), grid, dim3(kWave),
-                               0, stream, r);
-            break;
-        case 3:
-            hipLaunchKernelGGL((k_interact<kVariantChunk[3], kVariantWaves[3]>), grid, dim3(kWave),
-                               0, stream, r);
-            break;
-        default:
-            hipLaunchKernelGGL((k_interact<kVariantChunk[0], kVariantWaves[0]>), grid, dim3(kWave),
-                               0, stream, r);
-            break;
+        case 1: hipLaunchKernelGGL((MGRAV_VARIANT(1)), grid, dim3(kWave), 0, stream, r); break;
+        case 2: hipLaunchKernelGGL((MGRAV_VARIANT(2)), grid, dim3(kWave), 0, stream, r); break;
+        case 3: hipLaunchKernelGGL((MGRAV_VARIANT(3)), grid, dim3(kWave), 0, stream, r); break;
+        case 4: hipLaunchKernelGGL((MGRAV_VARIANT(4)), grid, dim3(kWave), 0, stream, r); break;
+        case 5: hipLaunchKernelGGL((MGRAV_VARIANT(5)), grid, dim3(kWave), 0, stream, r); break;
+        default: hipLaunchKernelGGL((MGRAV_VARIANT(0)), grid, dim3(kWave), 0, stream, r); break;
     }
 }
+#undef MGRAV_VARIANT
+static_assert(kNumVariants == 6, "interact_kernel and launch_interact list every variant");
 
 // ---------------------------------------------------------------------
 // Ewald correction (FP64)
@@ -1206,10 +1232,16 @@ struct mgrav_ctx {
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_e1 = nullptr;  // around k_interact / k_ewald
     bool have_run = false;
-    // graph cache: the captured launch sequence and the arguments it holds
-    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-    struct LaunchSet* g_set = nullptr;
+    // graph cache: the captured launch sequence and the arguments it holds,
+    // one set for computes that start with the staging of a fresh bind and
+    // one for those that do not (so alternating use never recaptures)
+    struct GraphSet {
+        hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+        hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+        struct LaunchSet* set = nullptr;
+    } gs[2];
+    int last_set = -1;            // graph set of the last compute
+    bool stage_pending = false;   // bound, staging kernels not yet enqueued
     bool no_graph = false;        // capture failed once: launch directly
     Control* host_ctl = nullptr;  // pinned
     MlpState mlp;
@@ -1218,6 +1250,9 @@ struct mgrav_ctx {
 // Everything a compute launches, compared byte-wise to decide whether the
 // captured graph can be replayed.
 struct LaunchSet {
+    int stage;     // 1: the staging kernels of a fresh bind run first
+    StageArgs s;   // their arguments (stage = 1)
+    Control* host_ctl;
     RunArgs r;
     EwaldArgs e;
     SurrogateArgs sg;
@@ -1246,15 +1281,22 @@ mgrav_status hip_fail(mgrav_ctx* c, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
-void drop_graph(mgrav_ctx* c) {
+void drop_set(mgrav_ctx* c, int k) {
+    mgrav_ctx::GraphSet& g = c->gs[k];
     for (int i = 0; i < 3; ++i) {
-        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
-        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
-        c->gexec[i] = nullptr;
-        c->graph[i] = nullptr;
+        if (g.gexec[i]) (void)hipGraphExecDestroy(g.gexec[i]);
+        if (g.graph[i]) (void)hipGraphDestroy(g.graph[i]);
+        g.gexec[i] = nullptr;
+        g.graph[i] = nullptr;
     }
-    delete c->g_set;
-    c->g_set = nullptr;
+    delete g.set;
+    g.set = nullptr;
+}
+
+void drop_graph(mgrav_ctx* c) {
+    drop_set(c, 0);
+    drop_set(c, 1);
+    c->last_set = -1;
 }
 
 StageArgs stage_args(mgrav_ctx* c) {
@@ -1431,18 +1473,9 @@ mgrav_status mgrav_bind(mgrav_ctx* c, const mgrav_problem* p, void* workspace, s
     else
         c->ewald = mgrav_ewald{MGRAV_EWALD_NONE, 2.6, 1, 10, 4, 1};
 
-    const StageArgs a = stage_args(c);
-    hipLaunchKernelGGL(k_init_control, dim3(1), dim3(kWave), 0, c->stream, a.ctl);
-    const int64_t nt = p->n_bucket * kBucket;
-    hipLaunchKernelGGL(k_stage_particles, dim3(unsigned((nt + 255) / 256)), dim3(256), 0,
-                       c->stream, a);
-    hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((p->n_cell + 255) / 256)), dim3(256), 0,
-                       c->stream, a);
-    hipLaunchKernelGGL(k_stage_pp, dim3(unsigned(p->n_bucket)), dim3(kWave), 0, c->stream, a);
-    hipLaunchKernelGGL(k_stage_pc, dim3(unsigned(p->n_bucket)), dim3(kWave), 0, c->stream, a);
-    HIP_TRY(c, hipGetLastError());
-    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, a.ctl, sizeof(Control), hipMemcpyDeviceToHost,
-                              c->stream));
+    // the staging kernels run at the start of the next compute (inside its
+    // first graph) or, if a wait comes first, at that wait
+    c->stage_pending = true;
     c->bound = true;
     return MGRAV_OK;
 }
@@ -1491,6 +1524,9 @@ mgrav_status mgrav_set_active(mgrav_ctx* c, const uint8_t* active_dev) {
 static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchSet* L) {
     std::memset(L, 0, sizeof(*L));  // padding too: the struct is compared byte-wise
     const mgrav_problem& p = c->prob;
+    L->stage = c->stage_pending ? 1 : 0;
+    if (L->stage) L->s = stage_args(c);
+    L->host_ctl = c->host_ctl;
     char* w = c->ws;
     RunArgs& r = L->r;
     r.n = p.n;
@@ -1566,11 +1602,24 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
 // 2 = Ewald.  Each phase is captured as its own graph so that timing
 // events can be recorded between them on the stream.
 static bool phase_used(const LaunchSet& L, int phase) {
-    return phase == 0 || (phase == 1 && L.tree) || (phase == 2 && L.ewald != MGRAV_EWALD_NONE);
+    // phase 2 always runs: it ends with the copy of the control block
+    return phase != 1 || L.tree;
+}
+
+// The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
+static void enqueue_stage(hipStream_t st, const StageArgs& a) {
+    hipLaunchKernelGGL(k_init_control, dim3(1), dim3(kWave), 0, st, a.ctl);
+    const int64_t nt = a.n_bucket * kBucket;
+    hipLaunchKernelGGL(k_stage_particles, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0, st,
+                       a);
+    hipLaunchKernelGGL(k_stage_pp, dim3(unsigned(a.n_bucket)), dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL(k_stage_pc, dim3(unsigned(a.n_bucket)), dim3(kWave), 0, st, a);
 }
 
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     if (phase == 0) {
+        if (L.stage) enqueue_stage(c->stream, L.s);
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
         hipLaunchKernelGGL(k_select, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256), 0,
                            c->stream, L.r);
@@ -1590,6 +1639,9 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)), dim3(256), 0,
                            c->stream, L.sg);
     }
+    if (phase == 2)
+        hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
+                           L.host_ctl);
 }
 
 // Capture the three phases; on any capture failure fall back to direct
@@ -1602,26 +1654,27 @@ static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
         c->no_graph = true;
         return;
     }
+    mgrav_ctx::GraphSet& g = c->gs[L.stage];
     for (int ph = 0; ph < 3; ++ph) {
         if (!phase_used(L, ph)) continue;
         hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             enqueue_phase(c, L, ph);
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(c->stream, &g);
-            if (e == hipSuccess && g) {
-                c->graph[ph] = g;
-                e = hipGraphInstantiate(&c->gexec[ph], g, nullptr, nullptr, 0);
+            hipGraph_t gr = nullptr;
+            e = hipStreamEndCapture(c->stream, &gr);
+            if (e == hipSuccess && gr) {
+                g.graph[ph] = gr;
+                e = hipGraphInstantiate(&g.gexec[ph], gr, nullptr, nullptr, 0);
             }
         }
-        if (e != hipSuccess || !c->gexec[ph]) {
+        if (e != hipSuccess || !g.gexec[ph]) {
             (void)hipGetLastError();
             drop_graph(c);
             c->no_graph = true;
             return;
         }
     }
-    c->g_set = new LaunchSet(L);
+    g.set = new LaunchSet(L);
 }
 
 mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot) {
@@ -1634,27 +1687,29 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
     HIP_TRY(c, hipSetDevice(c->device));
     LaunchSet L;
     make_launch(c, parts, acc, pot, &L);
-    const bool same = c->g_set && std::memcmp(c->g_set, &L, sizeof(L)) == 0;
+    mgrav_ctx::GraphSet& g = c->gs[L.stage];
+    const bool same = g.set && std::memcmp(g.set, &L, sizeof(L)) == 0;
     if (!same) {
-        drop_graph(c);
+        drop_set(c, L.stage);
         capture_graphs(c, L);
     }
     hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
     HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
     for (int ph = 0; ph < 3; ++ph) {
-        if (c->gexec[ph]) {
-            HIP_TRY(c, hipGraphLaunch(c->gexec[ph], c->stream));
+        if (g.gexec[ph]) {
+            HIP_TRY(c, hipGraphLaunch(g.gexec[ph], c->stream));
         } else {
             enqueue_phase(c, L, ph);
             HIP_TRY(c, hipGetLastError());
         }
         HIP_TRY(c, hipEventRecord(marks[ph], c->stream));
     }
-    // counters and error bits travel back with the work (pinned host copy)
-    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, c->ws + c->lay.ctl, sizeof(Control),
-                              hipMemcpyDeviceToHost, c->stream));
+    // counters and error bits travel back with the work: the last kernel of
+    // phase 2 copies the control block into pinned host memory
     HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
     c->have_run = true;
+    c->stage_pending = false;
+    c->last_set = L.stage;
     return MGRAV_OK;
 }
 
@@ -1667,6 +1722,14 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
     c->err.clear();
     if (!c->bound) return fail(c, MGRAV_ERR_STATE, "wait before bind");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (c->stage_pending) {  // bind without compute: stage now, for its checks
+        const StageArgs a = stage_args(c);
+        enqueue_stage(c->stream, a);
+        hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, a.ctl,
+                           c->host_ctl);
+        HIP_TRY(c, hipGetLastError());
+        c->stage_pending = false;
+    }
     // Watchdog: a marker event after all enqueued work, polled until done.
     hipEvent_t marker;
     HIP_TRY(c, hipEventCreateWithFlags(&marker, hipEventDisableTiming));
@@ -1693,7 +1756,8 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
         if (dt > 2e-3) std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.05 ? 50 : 500));
     }
     (void)hipEventDestroy(marker);
-    // host_ctl was filled by the copy enqueued at the end of bind / compute
+    // host_ctl was filled by the control copy at the end of the staging or
+    // of the last compute
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         if (c->have_run) {
@@ -1708,8 +1772,9 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
                 stats->ms_interact = ms;
             if (hipEventElapsedTime(&ms, c->ev_k1, c->ev_e1) == hipSuccess)
                 stats->ms_ewald = ms;
-            stats->graph_replay = c->gexec[0] != nullptr ? 1 : 0;
-            stats->interact_variant = c->g_set ? c->g_set->variant : c->variant;
+            const mgrav_ctx::GraphSet* g = c->last_set >= 0 ? &c->gs[c->last_set] : nullptr;
+            stats->graph_replay = g && g->gexec[0] != nullptr ? 1 : 0;
+            stats->interact_variant = g && g->set ? g->set->variant : c->variant;
         }
     }
     const int err = c->host_ctl->err;
@@ -1726,11 +1791,13 @@ mgrav_status mgrav_interact_variants(int* count) {
     return MGRAV_OK;
 }
 
-mgrav_status mgrav_interact_variant_info(int variant, int* pp_chunk, int* waves_per_simd) {
+mgrav_status mgrav_interact_variant_info(int variant, int* pp_chunk, int* waves_per_simd,
+                                         int* pc_prefetch) {
     if (variant < 0 || variant >= kNumVariants)
         return fail(nullptr, MGRAV_ERR_INVALID_ARG, "variant out of range");
     if (pp_chunk) *pp_chunk = kVariantChunk[variant];
     if (waves_per_simd) *waves_per_simd = kVariantWaves[variant];
+    if (pc_prefetch) *pc_prefetch = kVariantPrefetch[variant] ? 1 : 0;
     return MGRAV_OK;
 }
 

@@ -159,8 +159,9 @@ def test_every_interact_variant_matches_oracle(mg_ctx):
     tree, lists, pos_t, mass_t = prepared(ps)
     ao, _ = oracle.evaluate(tree, lists, pos_t, mass_t, ps.eps, mg.PART_PP | mg.PART_PC)
     try:
-        for v, (chunk, waves) in enumerate(mg.interact_variants()):
-            _case(f"interact variant {v} (pp_chunk {chunk}, waves {waves}) clustered_20")
+        for v, (chunk, waves, prefetch) in enumerate(mg.interact_variants()):
+            _case(f"interact variant {v} (pp_chunk {chunk}, waves {waves}, prefetch {prefetch}) "
+                  "clustered_20")
             ctx.set_interact_variant(v)
             ag, _, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, parts=mg.PART_PP | mg.PART_PC,
                             ewald=dict(mode=mg.EWALD_NONE))

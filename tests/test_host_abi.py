@@ -114,13 +114,15 @@ def test_calls_on_null_context_fail_cleanly():
 
 def test_interact_variants_and_their_argument_checks():
     v = mg.interact_variants()
-    assert len(v) >= 2 and v[0] == (48, 3)
-    for chunk, waves in v:
-        assert 1 <= chunk <= 64 and 1 <= waves <= 8
+    assert len(v) >= 2 and v[0] == (48, 3, 0)
+    for chunk, waves, prefetch in v:
+        assert 1 <= chunk <= 64 and 1 <= waves <= 8 and prefetch in (0, 1)
+        assert not prefetch or waves <= 2  # the prefetch needs the 2-wave register budget
     assert len(set(v)) == len(v)
     ch = ctypes.c_int(0)
-    assert mg._lib.mgrav_interact_variant_info(len(v), ctypes.byref(ch), None) == mg.ERR_INVALID_ARG
-    assert mg._lib.mgrav_interact_variant_info(-1, None, None) == mg.ERR_INVALID_ARG
+    assert mg._lib.mgrav_interact_variant_info(len(v), ctypes.byref(ch), None,
+                                               None) == mg.ERR_INVALID_ARG
+    assert mg._lib.mgrav_interact_variant_info(-1, None, None, None) == mg.ERR_INVALID_ARG
     assert mg._lib.mgrav_interact_variants(None) == mg.ERR_INVALID_ARG
     assert mg._lib.mgrav_set_interact_variant(None, 0) == mg.ERR_INVALID_ARG
     assert mg._lib.mgrav_autotune(None, None, None, None, 100.0, None, None) == mg.ERR_INVALID_ARG
