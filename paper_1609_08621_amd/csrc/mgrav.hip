@@ -83,7 +83,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
-    size_t ctl, pdat, work, items, bins, cellrec, ppent, pcent, ewald, total;
+    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, total;
 };
 
 Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, int64_t n_pc) {
@@ -103,8 +103,6 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(float) * kRec * n_cell);
     l.ppent = o;
     o += align256(sizeof(float4) * (n_pp > 0 ? n_pp : 1));
-    l.pcent = o;
-    o += align256(sizeof(float4) * (n_pc > 0 ? n_pc : 1));
     l.ewald = o;
     o += align256(sizeof(double) * (64 + 8 * kMaxHalfK));
     l.total = o;
@@ -138,7 +136,6 @@ struct StageArgs {
     BucketWork* work;
     float* cellrec;
     float4* ppent;
-    float4* pcent;
 };
 
 // The control block (counters, error bits) into pinned host memory: the
@@ -275,9 +272,11 @@ __device__ inline int block_sum(int v) {
     return v;
 }
 
-// (3a) PP entries: offset between the source bucket's centre (plus image
+// (3) PP entries: offset between the source bucket's centre (plus image
 // shift) and the sink bucket's centre, in double, rounded to float; the
-// source's first particle and count packed into the fourth word.
+// source's first particle and count packed into the fourth word.  Also
+// checks the bucket's PC range; the PC entries themselves are read, checked
+// and turned into offsets by the interact kernel.
 __global__ void __launch_bounds__(kWave) k_stage_pp(StageArgs a) {
     const int64_t b = blockIdx.x;
     const int lane = threadIdx.x;
@@ -311,6 +310,9 @@ __global__ void __launch_bounds__(kWave) k_stage_pp(StageArgs a) {
             a.ppent[e] = out;
         }
     }
+    const int64_t g0 = a.pc_off[b], g1 = a.pc_off[b + 1];
+    const bool pc_ok = g0 >= 0 && g0 <= g1 && g1 <= a.n_pc;
+    if (!pc_ok) bad = 1;
     bad = block_or(bad);
     self = block_or(self);
     nsrc = block_sum(nsrc);
@@ -320,46 +322,8 @@ __global__ void __launch_bounds__(kWave) k_stage_pp(StageArgs a) {
         a.work[b].nsrc = nsrc;
         a.work[b].pp0 = range_ok ? e0 : 0;
         a.work[b].pp1 = range_ok ? e1 : 0;
-    }
-}
-
-// (3b) PC entries: offset of the source's centre of mass (plus image
-// shift) from the sink bucket's centre, in the cell's length unit; the cell
-// index in the fourth word.  Reads the cell records, so it runs after (2).
-__global__ void __launch_bounds__(kWave) k_stage_pc(StageArgs a) {
-    const int64_t b = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int64_t s = a.bucket_cell[b];
-    const bool sink_ok = s >= 0 && s < a.n_cell;
-    const int64_t e0 = a.pc_off[b], e1 = a.pc_off[b + 1];
-    const bool range_ok = e0 >= 0 && e0 <= e1 && e1 <= a.n_pc;
-    double C[3] = {0, 0, 0};
-    if (sink_ok) bbox_centre(a.bbox, s, C);
-    int bad = (!range_ok || !sink_ok) ? 1 : 0;
-    if (range_ok) {
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
-            const int64_t src = a.pc_src[e];
-            const int img = a.pc_img[e];
-            // an invalid entry becomes a massless cell at the bucket centre
-            float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-            if (sink_ok && src >= 0 && src < a.n_cell && img < a.n_images) {
-                // the cell's 1/unit, staged by k_stage_cells (launched before)
-                const float t = a.cellrec[kRec * src + kRec - 1];
-                out.x = float(a.com[3 * src] + c_shift[img][0] * a.L - C[0]) * t;
-                out.y = float(a.com[3 * src + 1] + c_shift[img][1] * a.L - C[1]) * t;
-                out.z = float(a.com[3 * src + 2] + c_shift[img][2] * a.L - C[2]) * t;
-                out.w = __int_as_float(int(src));
-            } else {
-                bad = 1;
-            }
-            a.pcent[e] = out;
-        }
-    }
-    bad = block_or(bad);
-    if (lane == 0) {
-        if (bad) atomicOr(&a.ctl->err, kErrList);
-        a.work[b].pc0 = range_ok ? e0 : 0;
-        a.work[b].pc1 = range_ok ? e1 : 0;
+        a.work[b].pc0 = pc_ok && sink_ok ? g0 : 0;
+        a.work[b].pc1 = pc_ok && sink_ok ? g1 : 0;
     }
 }
 
@@ -376,7 +340,14 @@ struct RunArgs {
     signed char* bins;  // cost bin of each active bucket, -1 if inactive
     const float* __restrict__ cellrec;
     const float4* __restrict__ ppent;
-    const float4* __restrict__ pcent;
+    const int32_t* __restrict__ pc_src;       // [n_pc] source cell
+    const uint8_t* __restrict__ pc_img;       // [n_pc] image id
+    const double* __restrict__ com;           // [n_cell][3]
+    const double* __restrict__ bbox;          // [n_cell][6]
+    const int32_t* __restrict__ bucket_cell;  // [n_bucket]
+    int64_t n_cell;
+    double L;
+    int n_images;
     float* __restrict__ acc;  // [3][n]
     float* __restrict__ pot;  // [n]
     float eps2;
@@ -603,24 +574,27 @@ __device__ __forceinline__ T load_uniform(const T* p, int64_t i) {
 #endif
 }
 
-// PC entry f of a list ending at f1: the cell's offset (in its length
-// unit) and its record.  Entries at or past f1, and invalid cells, give zero
-// moments one unit away (t = 0 makes R' = (1, 0, 0) and D' = 1, so every
-// term is finite and adds zero).
-__device__ __forceinline__ void load_pc(const RunArgs& a, int64_t f, int64_t f1, float (&r)[kRec],
-                                        float& cx, float& cy, float& cz) {
+// PC entry f of a list ending at f1, for a sink bucket centred at C
+// (double): the cell's record and the offset of its centre of mass (plus
+// the image shift) from C, formed in double and scaled by the cell's
+// length unit before rounding to float.  An entry with a cell index or
+// image id out of range is reported (BAD_LIST) and, like entries at or past
+// f1, gives zero moments one unit away (t = 0 makes R' = (1, 0, 0) and
+// D' = 1, so every term is finite and adds zero).
+__device__ __forceinline__ void load_pc(const RunArgs& a, int64_t f, int64_t f1, double Cx,
+                                        double Cy, double Cz, float (&r)[kRec], float& cx,
+                                        float& cy, float& cz) {
     cx = -1.f;
     cy = 0.f;
     cz = 0.f;
-    int cell = -1;
+    int cell = -1, img = 0;
     if (f < f1) {
-        const float4 ent = a.pcent[f];
-        cell = __float_as_int(ent.w);
-        if (cell >= 0) {
-            cx = ent.x;
-            cy = ent.y;
-            cz = ent.z;
-        }
+        const int src = a.pc_src[f];
+        img = a.pc_img[f];
+        if (src >= 0 && src < a.n_cell && img < a.n_images)
+            cell = src;
+        else
+            atomicOr(&a.ctl->err, kErrList);
     }
     if (cell >= 0) {
         const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
@@ -632,6 +606,14 @@ __device__ __forceinline__ void load_pc(const RunArgs& a, int64_t f, int64_t f1,
             r[4 * i + 2] = q.z;
             r[4 * i + 3] = q.w;
         }
+        // image id 0 is the box, 1..26 the other points of {-1,0,1}^3 in
+        // lexicographic order: k is the position in the full 27-point order
+        const int k = img == 0 ? 13 : (img <= 13 ? img - 1 : img);
+        const double t = double(r[kRec - 1]);
+        const double* X = a.com + 3 * int64_t(cell);
+        cx = float((X[0] + double(k / 9 - 1) * a.L - Cx) * t);
+        cy = float((X[1] + double(k / 3 % 3 - 1) * a.L - Cy) * t);
+        cz = float((X[2] + double(k % 3 - 1) * a.L - Cz) * t);
     } else {
 #pragma unroll
         for (int i = 0; i < kRec; ++i) r[i] = 0.f;
@@ -679,6 +661,13 @@ __global__ void __launch_bounds__(kWave)
             item = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
             continue;
         }
+        // the sink bucket's centre (double; its cell was checked when staged)
+        const int64_t sc = load_uniform(a.bucket_cell, b);
+        const double Cx = 0.5 * (load_uniform(a.bbox, 6 * sc) + load_uniform(a.bbox, 6 * sc + 3));
+        const double Cy =
+            0.5 * (load_uniform(a.bbox, 6 * sc + 1) + load_uniform(a.bbox, 6 * sc + 4));
+        const double Cz =
+            0.5 * (load_uniform(a.bbox, 6 * sc + 2) + load_uniform(a.bbox, 6 * sc + 5));
 
         // The bucket's sink particles are wave-uniform: read them through the
         // constant address space so they arrive as scalar loads, all in flight
@@ -764,13 +753,14 @@ __global__ void __launch_bounds__(kWave)
                 // the next chunk's records load while this one computes
                 // (44 more registers: the 2-wave variants have them)
                 float rn[kRec], nx, ny, nz;
-                load_pc(a, f0 + lane, f1, rn, nx, ny, nz);
+                load_pc(a, f0 + lane, f1, Cx, Cy, Cz, rn, nx, ny, nz);
                 for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
                     float r[kRec];
 #pragma unroll
                     for (int i = 0; i < kRec; ++i) r[i] = rn[i];
                     const float cx = nx, cy = ny, cz = nz;
-                    if (c0 + kWave < f1) load_pc(a, c0 + kWave + lane, f1, rn, nx, ny, nz);
+                    if (c0 + kWave < f1)
+                        load_pc(a, c0 + kWave + lane, f1, Cx, Cy, Cz, rn, nx, ny, nz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
 #pragma unroll
@@ -780,7 +770,7 @@ __global__ void __launch_bounds__(kWave)
             } else {
                 for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
                     float r[kRec], cx, cy, cz;
-                    load_pc(a, c0 + lane, f1, r, cx, cy, cz);
+                    load_pc(a, c0 + lane, f1, Cx, Cy, Cz, r, cx, cy, cz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
 #pragma unroll
@@ -1331,7 +1321,6 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.work = reinterpret_cast<BucketWork*>(w + c->lay.work);
     a.cellrec = reinterpret_cast<float*>(w + c->lay.cellrec);
     a.ppent = reinterpret_cast<float4*>(w + c->lay.ppent);
-    a.pcent = reinterpret_cast<float4*>(w + c->lay.pcent);
     return a;
 }
 
@@ -1539,7 +1528,14 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     r.bins = reinterpret_cast<signed char*>(w + c->lay.bins);
     r.cellrec = reinterpret_cast<const float*>(w + c->lay.cellrec);
     r.ppent = reinterpret_cast<const float4*>(w + c->lay.ppent);
-    r.pcent = reinterpret_cast<const float4*>(w + c->lay.pcent);
+    r.pc_src = p.pc_src;
+    r.pc_img = p.pc_img;
+    r.com = p.com;
+    r.bbox = p.bbox;
+    r.bucket_cell = p.bucket_cell;
+    r.n_cell = p.n_cell;
+    r.L = p.box_L;
+    r.n_images = p.n_images;
     r.acc = acc;
     r.pot = pot;
     r.eps2 = float(p.eps * p.eps);
@@ -1614,7 +1610,6 @@ static void enqueue_stage(hipStream_t st, const StageArgs& a) {
     hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0, st,
                        a);
     hipLaunchKernelGGL(k_stage_pp, dim3(unsigned(a.n_bucket)), dim3(kWave), 0, st, a);
-    hipLaunchKernelGGL(k_stage_pc, dim3(unsigned(a.n_bucket)), dim3(kWave), 0, st, a);
 }
 
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {

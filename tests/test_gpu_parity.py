@@ -333,3 +333,13 @@ def test_bad_list_entry_is_reported_not_dereferenced(mg_ctx):
     with pytest.raises(mg.MgravError) as e:
         gpu(mg_ctx, ps, tree, bad, pos_t, mass_t)
     assert e.value.status == mg.ERR_BAD_LIST
+    # PC entries alone (checked where the interact kernel reads them)
+    for field, value in (("pc_src", 10 ** 7), ("pc_img", 27)):
+        bad = oracle.Lists(lists.pp_off, lists.pp_src, lists.pp_img.copy(), lists.pc_off,
+                           lists.pc_src.copy(), lists.pc_img.copy(), lists.n_images)
+        getattr(bad, field)[7] = value
+        _case(f"bad PC entry ({field} = {value}), PC part only -> BAD_LIST")
+        with pytest.raises(mg.MgravError) as e:
+            gpu(mg_ctx, ps, tree, bad, pos_t, mass_t, parts=mg.PART_PC,
+                ewald=dict(mode=mg.EWALD_NONE))
+        assert e.value.status == mg.ERR_BAD_LIST
