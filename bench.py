@@ -111,14 +111,30 @@ def main():
     tuned["pp_chunk"], tuned["waves_per_simd"], tuned["pc_prefetch"] = variants[tuned["index"]]
     print(f"[bench] PP + PC kernel variant {tuned}", file=sys.stderr, flush=True)
 
-    def step():
+    def enqueue():
+        # one step: re-stage the (moved) positions and compute every part
         ctx.bind(prob, tensors, ws)
         ctx.compute(acc, pot)
+
+    def step():
+        enqueue()
         return ctx.wait(60.0)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # throughput: the K steps are enqueued back to back on the stream, as a
+    # GPU-resident integrator would; the host waits (and the library checks
+    # the error bits) once, after the last step
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        enqueue()
+    st = ctx.wait(60.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    # kernel durations: the same K steps again, each waited for, reading the
+    # HIP events recorded around each phase on the context's stream
     ms_k, ms_e, ms_c = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -127,14 +143,14 @@ def main():
         ms_e.append(st.ms_ewald)
         ms_c.append(st.ms_total)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
+    ms_step_sync = 1e3 * (time.perf_counter() - t0) / args.steps
     n_int = st.n_pp_interactions + st.n_pc_interactions
     value = n_int / (ms_step * 1e-3)
     flops = st.n_pp_interactions * FLOP_PP + st.n_pc_interactions * FLOP_PC
     k_ms = float(np.mean(ms_k))
     achieved = flops / (k_ms * 1e-3) / 1e12
-    print(f"[bench] step {ms_step:.3f} ms (compute {np.mean(ms_c):.3f} ms: PP+PC kernel "
+    print(f"[bench] step {ms_step:.3f} ms back to back, {ms_step_sync:.3f} ms with a host wait "
+          f"per step (compute {np.mean(ms_c):.3f} ms: PP+PC kernel "
           f"{k_ms:.3f} ms, Ewald {np.mean(ms_e):.3f} ms), {value:.3e} interactions/s, "
           f"kernel {achieved:.1f} TFLOP/s", file=sys.stderr, flush=True)
 
@@ -161,6 +177,7 @@ def main():
         "particles_per_s": ps.n / (ms_step * 1e-3),
         "n_pp_interactions": st.n_pp_interactions,
         "n_pc_interactions": st.n_pc_interactions,
+        "ms_per_step_with_host_wait": ms_step_sync,
         "ms_compute": float(np.mean(ms_c)),
         "ms_interact_kernel": k_ms,
         "ms_ewald": float(np.mean(ms_e)),

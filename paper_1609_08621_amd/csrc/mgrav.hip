@@ -1639,8 +1639,9 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
                            L.host_ctl);
 }
 
-// Capture the three phases; on any capture failure fall back to direct
-// launches for this context.
+// Capture the three phases as one graph, with the timing events recorded
+// between them as external event nodes; on any capture failure fall back
+// to direct launches for this context.
 static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
     hipStreamCaptureStatus cs;
     if (c->no_graph || c->stream == nullptr ||
@@ -1650,24 +1651,31 @@ static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
         return;
     }
     mgrav_ctx::GraphSet& g = c->gs[L.stage];
-    for (int ph = 0; ph < 3; ++ph) {
-        if (!phase_used(L, ph)) continue;
-        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            enqueue_phase(c, L, ph);
-            hipGraph_t gr = nullptr;
-            e = hipStreamEndCapture(c->stream, &gr);
-            if (e == hipSuccess && gr) {
-                g.graph[ph] = gr;
-                e = hipGraphInstantiate(&g.gexec[ph], gr, nullptr, nullptr, 0);
-            }
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
+        hipError_t r = hipEventRecordWithFlags(c->ev_start, c->stream, hipEventRecordExternal);
+        for (int ph = 0; ph < 3 && r == hipSuccess; ++ph) {
+            if (phase_used(L, ph)) enqueue_phase(c, L, ph);
+            r = hipEventRecordWithFlags(marks[ph], c->stream, hipEventRecordExternal);
         }
-        if (e != hipSuccess || !g.gexec[ph]) {
-            (void)hipGetLastError();
-            drop_graph(c);
-            c->no_graph = true;
-            return;
+        if (r == hipSuccess)
+            r = hipEventRecordWithFlags(c->ev_end, c->stream, hipEventRecordExternal);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(c->stream, &gr);  // always end the capture
+        if (r != hipSuccess) e = r;
+        if (e == hipSuccess && gr) {
+            g.graph[0] = gr;
+            e = hipGraphInstantiate(&g.gexec[0], gr, nullptr, nullptr, 0);
+        } else if (gr) {
+            (void)hipGraphDestroy(gr);
         }
+    }
+    if (e != hipSuccess || !g.gexec[0]) {
+        (void)hipGetLastError();
+        drop_graph(c);
+        c->no_graph = true;
+        return;
     }
     g.set = new LaunchSet(L);
 }
@@ -1688,20 +1696,20 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
         drop_set(c, L.stage);
         capture_graphs(c, L);
     }
-    hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
-    HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
-    for (int ph = 0; ph < 3; ++ph) {
-        if (g.gexec[ph]) {
-            HIP_TRY(c, hipGraphLaunch(g.gexec[ph], c->stream));
-        } else {
+    if (g.gexec[0]) {
+        HIP_TRY(c, hipGraphLaunch(g.gexec[0], c->stream));
+    } else {
+        const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
+        HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+        for (int ph = 0; ph < 3; ++ph) {
             enqueue_phase(c, L, ph);
             HIP_TRY(c, hipGetLastError());
+            HIP_TRY(c, hipEventRecord(marks[ph], c->stream));
         }
-        HIP_TRY(c, hipEventRecord(marks[ph], c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
     }
     // counters and error bits travel back with the work: the last kernel of
     // phase 2 copies the control block into pinned host memory
-    HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
     c->have_run = true;
     c->stage_pending = false;
     c->last_set = L.stage;
