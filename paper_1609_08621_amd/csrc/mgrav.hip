@@ -978,6 +978,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
     if (threadIdx.x == 0) a.table[44] = double(nk < kMaxHalfK ? nk : kMaxHalfK);
 }
 
+#include "erfcx_poly.inc"
+
 // 1/(2j + 11) and 1/(j + 1) for the power series, 1/(2n + 1) for the
 // downward recurrence: constants, so the loops below divide nothing.
 struct EwaldConsts {
@@ -1029,7 +1031,18 @@ __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
     const double inv_r = 1.0 / r;
     const double inv_r2 = inv_r * inv_r;
     if (near) {
-        g[0] = erf(alpha * r) * inv_r;
+        // erf(z) = 1 - e^{-z^2} erfcx(z) for z = alpha r >= sqrt(2), with the
+        // exponential already at hand and erfcx from its polynomial in 2/z;
+        // beyond z = 6.5, e^{-z^2} erfcx(z) < 1e-19 and erf(z) = 1 in double
+        double er = 1.0;
+        if (alpha * r < 6.5) {
+            const double t = fma((2.0 / alpha) * kErfcxScale, inv_r, kErfcxShift);
+            double h = c_erfcx[kErfcxDeg];
+#pragma unroll
+            for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, c_erfcx[k]);
+            er = fma(-E, h, 1.0);
+        }
+        g[0] = er * inv_r;
 #pragma unroll
         for (int n = 0; n < 5; ++n) g[n + 1] = -(double(2 * n + 1) * g[n] + k[n + 1] * E) * inv_r2;
     } else {
