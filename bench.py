@@ -144,6 +144,7 @@ def main():
         ms_c.append(st.ms_total)
     torch.cuda.synchronize()
     ms_step_sync = 1e3 * (time.perf_counter() - t0) / args.steps
+    tuned["launch"] = "graph" if st.graph_replay else "direct"
     n_int = st.n_pp_interactions + st.n_pc_interactions
     value = n_int / (ms_step * 1e-3)
     flops = st.n_pp_interactions * FLOP_PP + st.n_pc_interactions * FLOP_PC
@@ -271,7 +272,12 @@ def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
     a_ref = ao[idx]
     err = float(np.sqrt(np.mean(np.sum((ag - a_ref) ** 2, 1) / np.sum(a_ref ** 2, 1))))
     pg = pot_dev.cpu().numpy()[idx]
-    perr = float(np.sqrt(np.sum((pg - po[idx]) ** 2) / np.sum(po[idx] ** 2)))
+    # the periodic total potential is a small residual of the PP + PC part
+    # and the Ewald correction, so the potential error is taken relative to
+    # the PP + PC part (total minus the oracle's correction; untimed)
+    _, pe = oracle.evaluate(to, lo, pos_t, mass_t, ps.eps, 4, buckets=sel)
+    tree_part = po[idx] - pe[idx]
+    perr = float(np.sqrt(np.sum((pg - po[idx]) ** 2) / np.sum(tree_part ** 2)))
     return {
         "value": n_int / dt,
         "unit": "interactions/s",
@@ -285,6 +291,7 @@ def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
         "seconds": dt,
         "gpu_rms_rel_acc_err_vs_oracle": err,
         "gpu_rel_pot_err_vs_oracle": perr,
+        "pot_err_normalisation": "rms of the oracle's PP + PC potential",
     }
 
 

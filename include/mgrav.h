@@ -280,6 +280,8 @@ typedef struct {
     double ms_ewald;             /* Ewald kernels of the last compute        */
     int graph_replay;            /* 1: launched from captured HIP graphs     */
     int interact_variant;        /* PP + PC kernel variant of the last compute */
+    int graph_error;             /* 0, or the HIP error code that made this  */
+                                 /* context fall back to direct launches     */
 } mgrav_stats;
 
 /* Wait for the context's work with a watchdog: polls the completion event
@@ -368,22 +370,33 @@ mgrav_status mgrav_mlp_train(mgrav_ctx *ctx, const double *u, const double *psi,
  *   variant (the first run of each untimed, then at least two timed runs,
  *   more while `budget_ms` of wall time lasts), keeps the variant with the
  *   smallest median kernel time for later computes and stores it in
- *   `*chosen` (nullable).  `acc`/`pot` (device, as for mgrav_compute) are
- *   overwritten by the trial runs.  `ms_per_variant` (host, nullable,
- *   mgrav_interact_variants() entries) receives each median, or -1 when not
- *   timed.  `cache_path` (nullable) names a text file of lines
- *   "mgrav-autotune <key> <variant>", the key being device, CU count and the
- *   list shape (n, buckets, PP and PC entries, images): a matching line is
- *   used without timing; otherwise the result is appended.  If the file
- *   cannot be appended to, the chosen variant still applies and the call
- *   returns INVALID_ARG.  STATE before bind; errors of the trial computes
- *   are returned as they are.  Blocking. */
+ *   `*chosen` (nullable).  Then it times 12 back-to-back computes of every
+ *   part from a graph and from direct launches and keeps the faster launch
+ *   mode (mgrav_set_launch_mode).  `acc`/`pot` (device, as for
+ *   mgrav_compute) are overwritten by the trial runs.  `ms_per_variant`
+ *   (host, nullable, mgrav_interact_variants() entries) receives each
+ *   median, or -1 when not timed.  `cache_path` (nullable) names a text file
+ *   of lines "mgrav-autotune <key> <variant> <launch mode>", the key being
+ *   device, CU count and the list shape (n, buckets, PP and PC entries,
+ *   images): a matching line is used without timing; otherwise the result is
+ *   appended.  If the file cannot be appended to, the choices still apply
+ *   and the call returns INVALID_ARG.  STATE before bind; errors of the trial
+ *   computes are returned as they are.  Blocking. */
 mgrav_status mgrav_interact_variants(int *count);
 mgrav_status mgrav_interact_variant_info(int variant, int *pp_chunk, int *waves_per_simd,
                                          int *pc_prefetch);
 mgrav_status mgrav_set_interact_variant(mgrav_ctx *ctx, int variant);
 mgrav_status mgrav_autotune(mgrav_ctx *ctx, float *acc, float *pot, const char *cache_path,
                             double budget_ms, int *chosen, double *ms_per_variant);
+
+/* How a compute is launched: MGRAV_LAUNCH_GRAPH (default) replays one HIP
+ * graph per compute (captured at the first compute with a given set of
+ * arguments); MGRAV_LAUNCH_DIRECT enqueues the kernels one by one.  Results
+ * are identical; which is faster depends on the runtime (mgrav_stats
+ * graph_replay tells which one the last compute used).  INVALID_ARG for
+ * another value. */
+enum { MGRAV_LAUNCH_GRAPH = 0, MGRAV_LAUNCH_DIRECT = 1 };
+mgrav_status mgrav_set_launch_mode(mgrav_ctx *ctx, int mode);
 
 #ifdef __cplusplus
 }

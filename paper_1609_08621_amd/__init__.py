@@ -35,6 +35,7 @@ OK, ERR_INVALID_ARG, ERR_BAD_TREE, ERR_BAD_LIST, ERR_DEVICE, ERR_NO_MEMORY, \
     ERR_TIMEOUT, ERR_STATE, ERR_NOT_TRAINED = range(9)
 PART_PP, PART_PC, PART_EWALD, PART_ALL = 1, 2, 4, 7
 EWALD_NONE, EWALD_EXACT, EWALD_SURROGATE = 0, 1, 2
+LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 MAX_BUCKET = 16
 
 
@@ -57,7 +58,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_pp_interactions", _I64), ("n_pc_interactions", _I64),
                 ("n_active_buckets", _I64), ("n_active_particles", _I64),
                 ("ms_total", _D), ("ms_interact", _D), ("ms_ewald", _D),
-                ("graph_replay", _I), ("interact_variant", _I)]
+                ("graph_replay", _I), ("interact_variant", _I), ("graph_error", _I)]
 
 
 class TrainConfig(ctypes.Structure):
@@ -127,6 +128,8 @@ def _declare():
     L.mgrav_set_interact_variant.argtypes = [_P, _I]
     L.mgrav_autotune.restype = _I
     L.mgrav_autotune.argtypes = [_P, _P, _P, ctypes.c_char_p, _D, ctypes.POINTER(_I), _P]
+    L.mgrav_set_launch_mode.restype = _I
+    L.mgrav_set_launch_mode.argtypes = [_P, _I]
 
 
 _declare()
@@ -140,7 +143,7 @@ EXPORTS = (
     "mgrav_ewald_psi", "mgrav_mlp_workspace_size", "mgrav_mlp_attach", "mgrav_mlp_set_weights",
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
     "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
-    "mgrav_autotune",
+    "mgrav_autotune", "mgrav_set_launch_mode",
 )
 
 
@@ -370,6 +373,10 @@ class Context:
         cfg = EwaldConfig(int(mode), float(alpha), int(real_layers), int(h2max), int(order),
                           int(top_cells))
         _check(_lib.mgrav_set_ewald(self._h, ctypes.byref(cfg)), self._h)
+
+    def set_launch_mode(self, mode: int):
+        """LAUNCH_GRAPH (one HIP graph per compute) or LAUNCH_DIRECT."""
+        _check(_lib.mgrav_set_launch_mode(self._h, int(mode)), self._h)
 
     def set_interact_variant(self, variant: int):
         _check(_lib.mgrav_set_interact_variant(self._h, int(variant)), self._h)

@@ -1,5 +1,6 @@
 """Build libmgrav.so in-tree: HIP kernels for gfx950 plus the host-side
-tree builder (g++ with OpenMP).  Run ``python -m paper_1609_08621_amd.build``."""
+tree builder (g++ with OpenMP).  Run ``python paper_1609_08621_amd/build.py``
+(by path: importing the package loads the library this replaces)."""
 from __future__ import annotations
 
 import os

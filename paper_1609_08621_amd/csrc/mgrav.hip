@@ -1246,6 +1246,8 @@ struct mgrav_ctx {
     int last_set = -1;            // graph set of the last compute
     bool stage_pending = false;   // bound, staging kernels not yet enqueued
     bool no_graph = false;        // capture failed once: launch directly
+    int graph_error = 0;          // the HIP error that made it fail
+    bool direct = false;          // MGRAV_LAUNCH_DIRECT chosen: no graphs
     Control* host_ctl = nullptr;  // pinned
     MlpState mlp;
 };
@@ -1652,45 +1654,86 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
                            L.host_ctl);
 }
 
-// Capture the three phases as one graph, with the timing events recorded
-// between them as external event nodes; on any capture failure fall back
-// to direct launches for this context.
+// One graph per compute: each phase is captured into a graph of its own,
+// and a parent graph chains them as child-graph nodes with the context's
+// timing events as event-record nodes in between (ev_start, phase 0,
+// ev_k0, phase 1, ev_k1, phase 2, ev_e1, ev_end).  The parent is built
+// explicitly because the HIP runtime PyTorch ships rejects event records
+// inside a stream capture.  On any failure the context falls back to
+// direct launches, and graph_error = 1000 * step + HIP error records why
+// (steps 1-3: capture of phase 0-2, 4: parent, 5: its nodes, 6:
+// instantiation).
 static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
     hipStreamCaptureStatus cs;
-    if (c->no_graph || c->stream == nullptr ||
-        hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    if (c->no_graph) return;
+    if (c->stream == nullptr) {  // the legacy default stream cannot be captured
+        c->no_graph = true;
+        c->graph_error = int(hipErrorInvalidValue);
+        return;
+    }
+    hipError_t q = hipStreamIsCapturing(c->stream, &cs);
+    if (q != hipSuccess || cs != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
         c->no_graph = true;
+        c->graph_error = q != hipSuccess ? int(q) : int(hipErrorStreamCaptureUnsupported);
         return;
     }
     mgrav_ctx::GraphSet& g = c->gs[L.stage];
-    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
-        hipError_t r = hipEventRecordWithFlags(c->ev_start, c->stream, hipEventRecordExternal);
-        for (int ph = 0; ph < 3 && r == hipSuccess; ++ph) {
-            if (phase_used(L, ph)) enqueue_phase(c, L, ph);
-            r = hipEventRecordWithFlags(marks[ph], c->stream, hipEventRecordExternal);
-        }
-        if (r == hipSuccess)
-            r = hipEventRecordWithFlags(c->ev_end, c->stream, hipEventRecordExternal);
-        hipGraph_t gr = nullptr;
-        e = hipStreamEndCapture(c->stream, &gr);  // always end the capture
-        if (r != hipSuccess) e = r;
-        if (e == hipSuccess && gr) {
-            g.graph[0] = gr;
-            e = hipGraphInstantiate(&g.gexec[0], gr, nullptr, nullptr, 0);
-        } else if (gr) {
-            (void)hipGraphDestroy(gr);
-        }
+    int step = 0;
+    hipError_t e = hipSuccess;
+    hipGraph_t phase[3] = {nullptr, nullptr, nullptr};
+    for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) {
+        if (!phase_used(L, ph)) continue;
+        step = 1 + ph;
+        e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) break;
+        enqueue_phase(c, L, ph);
+        const hipError_t r = hipPeekAtLastError();
+        const hipError_t ec = hipStreamEndCapture(c->stream, &phase[ph]);  // always end it
+        e = r != hipSuccess ? r : ec;
     }
-    if (e != hipSuccess || !g.gexec[0]) {
-        (void)hipGetLastError();
-        drop_graph(c);
-        c->no_graph = true;
+    hipGraph_t parent = nullptr;
+    if (e == hipSuccess) {
+        step = 4;
+        e = hipGraphCreate(&parent, 0);
+    }
+    hipGraphNode_t prev = nullptr;
+    auto chain_event = [&](hipEvent_t ev) {
+        hipGraphNode_t n = nullptr;
+        e = hipGraphAddEventRecordNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, ev);
+        prev = n;
+    };
+    auto chain_child = [&](hipGraph_t child) {
+        hipGraphNode_t n = nullptr;
+        e = hipGraphAddChildGraphNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, child);
+        prev = n;
+    };
+    if (e == hipSuccess) {
+        step = 5;
+        const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
+        chain_event(c->ev_start);
+        for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) {
+            if (phase[ph]) chain_child(phase[ph]);
+            if (e == hipSuccess) chain_event(marks[ph]);
+        }
+        if (e == hipSuccess) chain_event(c->ev_end);
+    }
+    if (e == hipSuccess) {
+        step = 6;
+        e = hipGraphInstantiate(&g.gexec[0], parent, nullptr, nullptr, 0);
+    }
+    for (hipGraph_t ph : phase)  // the parent holds copies
+        if (ph) (void)hipGraphDestroy(ph);
+    if (e == hipSuccess && g.gexec[0]) {
+        g.graph[0] = parent;
+        g.set = new LaunchSet(L);
         return;
     }
-    g.set = new LaunchSet(L);
+    if (parent) (void)hipGraphDestroy(parent);
+    (void)hipGetLastError();
+    drop_graph(c);
+    c->no_graph = true;
+    c->graph_error = 1000 * step + (e != hipSuccess ? int(e) : int(hipErrorUnknown));
 }
 
 mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot) {
@@ -1707,7 +1750,7 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
     const bool same = g.set && std::memcmp(g.set, &L, sizeof(L)) == 0;
     if (!same) {
         drop_set(c, L.stage);
-        capture_graphs(c, L);
+        if (!c->direct) capture_graphs(c, L);
     }
     if (g.gexec[0]) {
         HIP_TRY(c, hipGraphLaunch(g.gexec[0], c->stream));
@@ -1790,6 +1833,7 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
                 stats->ms_ewald = ms;
             const mgrav_ctx::GraphSet* g = c->last_set >= 0 ? &c->gs[c->last_set] : nullptr;
             stats->graph_replay = g && g->gexec[0] != nullptr ? 1 : 0;
+            stats->graph_error = c->graph_error;
             stats->interact_variant = g && g->set ? g->set->variant : c->variant;
         }
     }
@@ -1843,21 +1887,24 @@ mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* ca
     if (cache_path) {
         int hit = -1;
         if (FILE* f = std::fopen(cache_path, "r")) {
-            // lines "mgrav-autotune <key> <variant>"; other lines are
-            // ignored, the last match wins
+            // lines "mgrav-autotune <key> <variant> <launch mode>"; other
+            // lines are ignored, the last match wins
             char line[512], k[256];
-            int v = -1;
+            int v = -1, m = 0, hit_mode = 0;
             while (std::fgets(line, sizeof(line), f)) {
-                if (std::sscanf(line, "mgrav-autotune %255s %d", k, &v) == 2 &&
-                    std::strcmp(k, key) == 0 && v >= 0 && v < kNumVariants)
+                if (std::sscanf(line, "mgrav-autotune %255s %d %d", k, &v, &m) == 3 &&
+                    std::strcmp(k, key) == 0 && v >= 0 && v < kNumVariants && (m == 0 || m == 1)) {
                     hit = v;
+                    hit_mode = m;
+                }
             }
             std::fclose(f);
-        }
-        if (hit >= 0) {
-            c->variant = hit;
-            if (chosen) *chosen = hit;
-            return MGRAV_OK;
+            if (hit >= 0) {
+                c->variant = hit;
+                c->direct = hit_mode == MGRAV_LAUNCH_DIRECT;
+                if (chosen) *chosen = hit;
+                return MGRAV_OK;
+            }
         }
     }
     const int saved = c->variant;
@@ -1895,12 +1942,46 @@ mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* ca
     }
     c->variant = best_v;
     if (chosen) *chosen = best_v;
+    // launch mode: wall time of back-to-back computes of every part, from a
+    // graph and from direct launches (graphs kept unless direct is faster)
+    double per_mode[2] = {0.0, 0.0};
+    for (int mode = 0; mode < 2; ++mode) {
+        c->direct = mode == MGRAV_LAUNCH_DIRECT;
+        drop_graph(c);
+        mgrav_status st = MGRAV_OK;
+        for (int rep = 0; rep < 3 && st == MGRAV_OK; ++rep) {  // warm-up (captures)
+            st = mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
+            if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, nullptr);
+        }
+        const auto m0 = std::chrono::steady_clock::now();
+        for (int rep = 0; rep < 12 && st == MGRAV_OK; ++rep)
+            st = mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
+        if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, nullptr);
+        if (st != MGRAV_OK) {
+            c->direct = false;
+            return st;
+        }
+        per_mode[mode] =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - m0)
+                .count();
+    }
+    c->direct = per_mode[1] < per_mode[0];
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(c, MGRAV_ERR_INVALID_ARG, "cannot append to cache_path (variant applied)");
-        std::fprintf(f, "mgrav-autotune %s %d\n", key, best_v);
+        std::fprintf(f, "mgrav-autotune %s %d %d\n", key, best_v, c->direct ? 1 : 0);
         std::fclose(f);
     }
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_set_launch_mode(mgrav_ctx* c, int mode) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (mode != MGRAV_LAUNCH_GRAPH && mode != MGRAV_LAUNCH_DIRECT)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "mode must be MGRAV_LAUNCH_GRAPH or _DIRECT");
+    if (c->direct != (mode == MGRAV_LAUNCH_DIRECT)) drop_graph(c);
+    c->direct = mode == MGRAV_LAUNCH_DIRECT;
     return MGRAV_OK;
 }
 

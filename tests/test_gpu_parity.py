@@ -99,7 +99,7 @@ def check_parts(mg_ctx, ps, label, sample=None):
         res[name] = (rel_rms(ag, ao), glob_rel(ag, ao), perr)
         print(f"  {name}: rel_rms={res[name][0]:.3e} glob={res[name][1]:.3e} "
               f"pot={res[name][2]:.3e}  pp={st.n_pp_interactions} pc={st.n_pc_interactions} "
-              f"graph={st.graph_replay}", flush=True)
+              f"graph={st.graph_replay} ({st.graph_error})", flush=True)
     assert res["PP"][1] < TOL_PART and res["PC"][1] < TOL_PART
     if "EWALD" in res:
         assert res["EWALD"][1] < TOL_EWALD and res["EWALD"][2] < TOL_EWALD
@@ -188,13 +188,35 @@ def test_autotune_chooses_and_caches(mg_ctx, tmp_path):
         assert 0 <= v < len(ms) and all(m > 0 for m in ms)
         assert v == int(np.argmin(ms))
         lines = open(cache).read().split("\n")
-        assert lines[0].startswith("mgrav-autotune ") and lines[0].endswith(f" {v}")
+        mode = int(lines[0].split()[-1])
+        assert lines[0].startswith("mgrav-autotune ") and lines[0].split()[-2] == str(v)
+        assert mode in (mg.LAUNCH_GRAPH, mg.LAUNCH_DIRECT)
         v2, ms2 = ctx.autotune(acc, pot, cache_path=cache, budget_ms=500.0)
         assert v2 == v and all(m == -1.0 for m in ms2)
         ctx.compute(acc, pot)
-        assert ctx.wait(60).interact_variant == v
+        st = ctx.wait(60)
+        assert st.interact_variant == v
+        assert st.graph_replay == (1 if mode == mg.LAUNCH_GRAPH else 0)
     finally:
         ctx.set_interact_variant(0)
+        ctx.set_launch_mode(mg.LAUNCH_GRAPH)
+
+
+def test_launch_modes_give_identical_results(mg_ctx):
+    mg, ctx = mg_ctx
+    ps = workloads.make(3, scale_n1d=20)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    _case("graph and direct launches, clustered_20, bitwise equal")
+    out = {}
+    try:
+        for mode in (mg.LAUNCH_GRAPH, mg.LAUNCH_DIRECT):
+            ctx.set_launch_mode(mode)
+            a, p_, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t)
+            assert st.graph_replay == (1 if mode == mg.LAUNCH_GRAPH else 0), st.graph_error
+            out[mode] = (a, p_)
+    finally:
+        ctx.set_launch_mode(mg.LAUNCH_GRAPH)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
 def test_lattice_periodic_full_size_sampled(mg_ctx):
@@ -267,10 +289,15 @@ def test_repeat_is_bitwise_deterministic(mg_ctx):
     tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
     ctx.bind(p, tensors)
     outs = []
-    for _ in range(3):
-        acc, pot = ctx.outputs()
+    acc, pot = ctx.outputs()
+    for rep in range(4):
+        if rep == 3:  # new output buffers: a fresh capture
+            acc, pot = ctx.outputs()
         ctx.compute(acc, pot)
-        ctx.wait(60)
+        st = ctx.wait(60)
+        print(f"  compute {rep}: graph_replay={st.graph_replay} graph_error={st.graph_error}",
+              flush=True)
+        assert st.graph_replay == 1, f"graph capture fell back to direct launches ({st.graph_error})"
         outs.append((acc.cpu().numpy(), pot.cpu().numpy()))
     for a, p_ in outs[1:]:
         assert np.array_equal(a, outs[0][0]) and np.array_equal(p_, outs[0][1])
