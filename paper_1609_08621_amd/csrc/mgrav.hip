@@ -1027,15 +1027,18 @@ __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
         for (int n = 4; n >= 0; --n) g[n] = -(r2 * g[n + 1] + k[n + 1] * E) * c_ew.inv_2n1[n];
         return;
     }
-    const double r = sqrt(r2);
-    const double inv_r = 1.0 / r;
+    // 1/r from the hardware reciprocal square root refined by two Newton
+    // steps y <- y (3 - r2 y^2) / 2 (each squares the relative error)
+    double inv_r = __builtin_amdgcn_rsq(r2);
+    inv_r = inv_r * fma(-0.5 * r2, inv_r * inv_r, 1.5);
+    inv_r = inv_r * fma(-0.5 * r2, inv_r * inv_r, 1.5);
     const double inv_r2 = inv_r * inv_r;
     if (near) {
         // erf(z) = 1 - e^{-z^2} erfcx(z) for z = alpha r >= sqrt(2), with the
         // exponential already at hand and erfcx from its polynomial in 2/z;
         // beyond z = 6.5, e^{-z^2} erfcx(z) < 1e-19 and erf(z) = 1 in double
         double er = 1.0;
-        if (alpha * r < 6.5) {
+        if (x < 42.25) {  // z < 6.5
             const double t = fma((2.0 / alpha) * kErfcxScale, inv_r, kErfcxShift);
             double h = c_erfcx[kErfcxDeg];
 #pragma unroll
@@ -1046,7 +1049,7 @@ __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
 #pragma unroll
         for (int n = 0; n < 5; ++n) g[n + 1] = -(double(2 * n + 1) * g[n] + k[n + 1] * E) * inv_r2;
     } else {
-        double e = erfc(alpha * r) * inv_r;
+        double e = erfc(alpha * r2 * inv_r) * inv_r;
         g[0] = -e;
 #pragma unroll
         for (int n = 0; n < 5; ++n) {
