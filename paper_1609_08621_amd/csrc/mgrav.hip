@@ -1006,11 +1006,12 @@ __constant__ EwaldConsts c_ew = {
 // the rest by the downward recurrence g_n = -(r^2 g_{n+1} + k_{n+1} e^{-x})
 // / (2n+1) with k_m = (-2 alpha^2)^m / (alpha sqrt(pi)); otherwise upward
 // from the closed form (the same recurrence solved for g_{n+1}).
-__device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
+// E = exp(-alpha^2 r^2) is passed in (k_ewald builds it from per-axis
+// factors for the near images).
+__device__ void ewald_radial_e(double r2, double alpha, bool near, double E, double g[6]) {
     const double SQRT_PI = 1.77245385090551602729;
     const double al2 = alpha * alpha;
     const double x = al2 * r2;
-    const double E = exp(-x);
     double k[6];
     k[0] = 1.0 / (alpha * SQRT_PI);
 #pragma unroll
@@ -1059,6 +1060,10 @@ __device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
     }
 }
 
+__device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
+    ewald_radial_e(r2, alpha, near, exp(-alpha * alpha * r2), g);
+}
+
 struct TableRec {
     const double* t;
     __device__ double operator[](int i) const { return load_uniform(t, i); }
@@ -1085,6 +1090,17 @@ __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
     const double rz = (a.pos[3 * i + 2] - a.com[2]) * invL;
     double phi = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
     const int R = a.real_layers;
+    // exp(-alpha^2 |r - n|^2) of the 27 near images as products of per-axis
+    // factors exp(-alpha^2 (r_a - n_a)^2), n_a in {-1, 0, 1}: 9 exponentials
+    const double al2 = a.alpha * a.alpha;
+    double fxa[3], fya[3], fza[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double dx = rx - (k - 1), dy = ry - (k - 1), dz = rz - (k - 1);
+        fxa[k] = exp(-al2 * dx * dx);
+        fya[k] = exp(-al2 * dy * dy);
+        fza[k] = exp(-al2 * dz * dz);
+    }
     for (int ix = -R; ix <= R; ++ix)
         for (int iy = -R; iy <= R; ++iy)
             for (int iz = -R; iz <= R; ++iz) {
@@ -1093,8 +1109,18 @@ __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
                 asm volatile("" ::: "memory");
                 const bool near = ix >= -1 && ix <= 1 && iy >= -1 && iy <= 1 && iz >= -1 && iz <= 1;
                 const double x = rx - ix, y = ry - iy, z = rz - iz;
+                const double r2 = x * x + y * y + z * z;
+                double E;
+                if (near) {  // wave-uniform selects, no indexed registers
+                    const double fx = ix < 0 ? fxa[0] : (ix == 0 ? fxa[1] : fxa[2]);
+                    const double fy = iy < 0 ? fya[0] : (iy == 0 ? fya[1] : fya[2]);
+                    const double fz = iz < 0 ? fza[0] : (iz == 0 ? fza[1] : fza[2]);
+                    E = fx * fy * fz;
+                } else {
+                    E = exp(-al2 * r2);
+                }
                 double g[6];
-                ewald_radial(x * x + y * y + z * z, a.alpha, near, g);
+                ewald_radial_e(r2, a.alpha, near, E, g);
                 double P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
                 multipole_terms<double>(rec, x, y, z, P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z,
                                         v4x, v4y, v4z);
@@ -1589,7 +1615,8 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         L->n_cell = p.n_cell;
         const int per_group = 16 / (g.ncell < 16 ? g.ncell : 16);
         const int64_t groups = (p.n + per_group - 1) / per_group;
-        const int64_t blocks = (groups + 3) / 4;
+        const int64_t wpb = kSurrogateThreads / kWave;
+        const int64_t blocks = (groups + wpb - 1) / wpb;
         L->surrogate_blocks = int(blocks < 8 * c->n_cu ? blocks : 8 * c->n_cu);
     }
     if (L->ewald == MGRAV_EWALD_EXACT) {
@@ -1649,7 +1676,8 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE) {
         hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.com,
                            L.mom, L.n_cell, L.sg.ncell, const_cast<double*>(L.sg.cells));
-        hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)), dim3(256), 0,
+        hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)),
+                           dim3(kSurrogateThreads), 0,
                            c->stream, L.sg);
     }
     if (phase == 2)
