@@ -129,8 +129,6 @@ struct StageArgs {
     const int32_t* __restrict__ pp_src;
     const uint8_t* __restrict__ pp_img;
     const int64_t* __restrict__ pc_off;
-    const int32_t* __restrict__ pc_src;
-    const uint8_t* __restrict__ pc_img;
     Control* ctl;
     float4* pdat;
     BucketWork* work;
@@ -1357,8 +1355,6 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.pp_src = p.pp_src;
     a.pp_img = p.pp_img;
     a.pc_off = p.pc_off;
-    a.pc_src = p.pc_src;
-    a.pc_img = p.pc_img;
     char* w = c->ws;
     a.ctl = reinterpret_cast<Control*>(w + c->lay.ctl);
     a.pdat = reinterpret_cast<float4*>(w + c->lay.pdat);
