@@ -45,7 +45,7 @@ extern "C" {
 #endif
 
 #define MGRAV_VERSION_MAJOR 0
-#define MGRAV_VERSION_MINOR 1
+#define MGRAV_VERSION_MINOR 2
 
 /* Largest bucket (leaf) the device kernels accept; the paper's optimum
  * bucket size is about 16 (Sec. 3.1). */
@@ -222,11 +222,28 @@ mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace,
  * `top_cells` (1 = root, 8 or 64) tree cells at depth log2(top_cells)
  * (a leaf met earlier stands for its branch), psi from the network at
  * every (particle, cell) pair, added in double.  SURROGATE without weights
- * fails NOT_TRAINED; another top_cells value fails INVALID_ARG. */
+ * fails NOT_TRAINED; another top_cells value fails INVALID_ARG.
+ *
+ * SURROGATE_FALLBACK keeps the exact sums as the judge of the network and
+ * its fallback, decided on the device at every compute: the exact
+ * correction and the surrogate are evaluated at the sample of particles
+ * j * sample_stride (j = 0, 1, ...; active ones only), and
+ *   err = sqrt( mean |a_surrogate - a_exact|^2 / |a_base + a_exact|^2 )
+ * over that sample (the rms relative force error the surrogate adds),
+ * a_base being the PP + PC acceleration already in acc (zero when the
+ * compute leaves out PP and PC, so err is then relative to the correction
+ * itself).  If err <= fallback_tol the surrogate is applied
+ * to every active particle, else the exact correction (alpha, real_layers,
+ * h2max, order as for EXACT); an empty sample also takes the exact path.
+ * mgrav_stats reports err, the sample size and which path ran.  The
+ * sample holds at most 16384 particles: sample_stride 0 picks
+ * ceil(n / 8192), and a smaller stride than ceil(n / 16384) is raised to
+ * it.  Needs weights (NOT_TRAINED) and valid parameters for both modes. */
 typedef enum {
     MGRAV_EWALD_NONE = 0,
     MGRAV_EWALD_EXACT = 1,
-    MGRAV_EWALD_SURROGATE = 2
+    MGRAV_EWALD_SURROGATE = 2,
+    MGRAV_EWALD_SURROGATE_FALLBACK = 3
 } mgrav_ewald_mode;
 
 typedef struct {
@@ -236,10 +253,14 @@ typedef struct {
     int h2max;         /* k-space terms with 0 < |h|^2 <= h2max (0..64)    */
     int order;         /* 0, 2 or 4 (moments of the root used)             */
     int top_cells;     /* surrogate: 1 = root monopole, 8 or 64 cells      */
+    double fallback_tol; /* SURROGATE_FALLBACK: largest accepted err (>= 0) */
+    int64_t sample_stride; /* SURROGATE_FALLBACK: 0 = default (see above)  */
 } mgrav_ewald;
 
-/* Defaults after bind: EXACT with alpha 2.6, real_layers 1, h2max 10,
- * order 4 when box_L > 0; NONE when open. */
+/* Defaults after every bind: EXACT with alpha 2.6, real_layers 1,
+ * h2max 10, order 4 (top_cells 1, fallback_tol 1e-4, sample_stride 0) when
+ * box_L > 0; NONE when open.  Call it again after each bind to keep
+ * another setting. */
 mgrav_status mgrav_set_ewald(mgrav_ctx *ctx, const mgrav_ewald *cfg);
 
 /* Active particles of an individual-time-step substep (Sec. 3.2): only
@@ -282,6 +303,10 @@ typedef struct {
     int interact_variant;        /* PP + PC kernel variant of the last compute */
     int graph_error;             /* 0, or the HIP error code that made this  */
                                  /* context fall back to direct launches     */
+    int ewald_fallback;          /* SURROGATE_FALLBACK: 1 = the exact path   */
+                                 /* ran, 0 = the surrogate was accepted      */
+    int64_t ewald_samples;       /* SURROGATE_FALLBACK: active sample size   */
+    double ewald_sample_err;     /* SURROGATE_FALLBACK: err of the sample    */
 } mgrav_stats;
 
 /* Wait for the context's work with a watchdog: polls the completion event

@@ -34,7 +34,7 @@ _D = ctypes.c_double
 OK, ERR_INVALID_ARG, ERR_BAD_TREE, ERR_BAD_LIST, ERR_DEVICE, ERR_NO_MEMORY, \
     ERR_TIMEOUT, ERR_STATE, ERR_NOT_TRAINED = range(9)
 PART_PP, PART_PC, PART_EWALD, PART_ALL = 1, 2, 4, 7
-EWALD_NONE, EWALD_EXACT, EWALD_SURROGATE = 0, 1, 2
+EWALD_NONE, EWALD_EXACT, EWALD_SURROGATE, EWALD_SURROGATE_FALLBACK = 0, 1, 2, 3
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 MAX_BUCKET = 16
 
@@ -51,14 +51,16 @@ class Problem(ctypes.Structure):
 
 class EwaldConfig(ctypes.Structure):
     _fields_ = [("mode", _I), ("alpha", _D), ("real_layers", _I), ("h2max", _I),
-                ("order", _I), ("top_cells", _I)]
+                ("order", _I), ("top_cells", _I), ("fallback_tol", _D),
+                ("sample_stride", _I64)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_pp_interactions", _I64), ("n_pc_interactions", _I64),
                 ("n_active_buckets", _I64), ("n_active_particles", _I64),
                 ("ms_total", _D), ("ms_interact", _D), ("ms_ewald", _D),
-                ("graph_replay", _I), ("interact_variant", _I), ("graph_error", _I)]
+                ("graph_replay", _I), ("interact_variant", _I), ("graph_error", _I),
+                ("ewald_fallback", _I), ("ewald_samples", _I64), ("ewald_sample_err", _D)]
 
 
 class TrainConfig(ctypes.Structure):
@@ -369,9 +371,10 @@ class Context:
                                ctypes.c_size_t(workspace.numel())), self._h)
 
     def set_ewald(self, mode: int = EWALD_EXACT, alpha: float = 2.6, real_layers: int = 1,
-                  h2max: int = 10, order: int = 4, top_cells: int = 1):
+                  h2max: int = 10, order: int = 4, top_cells: int = 1,
+                  fallback_tol: float = 1e-4, sample_stride: int = 0):
         cfg = EwaldConfig(int(mode), float(alpha), int(real_layers), int(h2max), int(order),
-                          int(top_cells))
+                          int(top_cells), float(fallback_tol), int(sample_stride))
         _check(_lib.mgrav_set_ewald(self._h, ctypes.byref(cfg)), self._h)
 
     def set_launch_mode(self, mode: int):

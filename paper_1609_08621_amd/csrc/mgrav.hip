@@ -59,6 +59,10 @@ struct Control {
     unsigned long long n_active_b;
     int bin_count[kCostBins];   // active buckets per cost bin
     int bin_cursor[kCostBins];  // next queue slot of each bin
+    double ew_err;                  // surrogate judge: error of the sample
+    unsigned long long ew_samples;  // surrogate judge: active particles sampled
+    int ew_fallback;                // surrogate judge: 1 = exact path taken
+    int ew_pad;
 };
 
 // Image shifts in units of L: id 0 the box, 1..26 lexicographic {-1,0,1}^3.
@@ -83,8 +87,15 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
-    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, total;
+    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, total;
 };
+
+// Sample of the surrogate judge: at most kMaxEwaldSamples particles, one
+// record of kSampleRec doubles each (exact acceleration, valid flag, the
+// PP + PC acceleration before the correction, the surrogate's acceleration).
+constexpr int64_t kMaxEwaldSamples = 16384;
+constexpr int64_t kDefaultEwaldSamples = 8192;
+constexpr int kSampleRec = 12;
 
 Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, int64_t n_pc) {
     Layout l{};
@@ -105,6 +116,8 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(float4) * (n_pp > 0 ? n_pp : 1));
     l.ewald = o;
     o += align256(sizeof(double) * (64 + 8 * kMaxHalfK));
+    l.ewsample = o;
+    o += align256(sizeof(double) * kSampleRec * kMaxEwaldSamples);
     l.total = o;
     return l;
 }
@@ -151,6 +164,9 @@ __global__ void k_init_control(Control* ctl) {
         ctl->n_items = 0;
         ctl->head = 0;
         ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
+        ctl->ew_err = 0.0;
+        ctl->ew_samples = 0;
+        ctl->ew_fallback = 0;
     }
 }
 
@@ -225,9 +241,9 @@ __device__ float cell_inv_unit(const StageArgs& a, int64_t c) {
     return float(ldexp(1.0, -e));
 }
 
-// (2) cells: float coefficients of the order-4 expansion (see pc_terms),
-// the order-k ones in units of the cell's length unit (times t^k), and
-// t = 1 / unit in the last word.
+// (2) cells: float coefficients of the order-4 expansion (multipole_terms,
+// pc_one), the order-k ones in units of the cell's length unit (times t^k),
+// and t = 1 / unit in the last word.
 __global__ void k_stage_cells(StageArgs a) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
@@ -248,6 +264,10 @@ __global__ void k_stage_cells(StageArgs a) {
     r[26] = 0.25 * (m[21] + m[28] + m[30]);
     r[27] = 0.25 * (m[22] + m[29] + m[31]);
     for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0;
+    // the group of each radial derivative a_n carries its (2n - 1)!! (see pc_one)
+    for (int i = 2; i < 12; ++i) r[i] *= 3.0;
+    for (int i = 12; i < 28; ++i) r[i] *= 15.0;
+    for (int i = 28; i < 43; ++i) r[i] *= 105.0;
     const double t = cell_inv_unit(a, c), t2 = t * t, t3 = t2 * t, t4 = t3 * t;
     for (int i = 1; i < 8; ++i) r[i] *= t2;
     for (int i = 8; i < 11; ++i) r[i] *= t3;
@@ -357,6 +377,9 @@ __global__ void k_reset(Control* ctl) {
         ctl->n_items = 0;
         ctl->head = 0;
         ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
+        ctl->ew_err = 0.0;
+        ctl->ew_samples = 0;
+        ctl->ew_fallback = 0;
     }
     if (threadIdx.x < kCostBins) ctl->bin_count[threadIdx.x] = 0;
 }
@@ -463,9 +486,11 @@ __global__ void __launch_bounds__(256) k_order_scatter(RunArgs a) {
 // with P_0 = M, P_1 = tr(M2)/2, P_2 = R.M2.R/2 - tr(M3).R/2 + tr tr(M4)/8,
 // P_3 = -M3[RRR]/6 + R.tr(M4).R/4, P_4 = M4[RRRR]/24: the Taylor series of
 // the softened potential about the centre of mass, grouped by radial
-// derivative.  The staged record holds the scaled moment combinations
+// derivative.  The coefficients are the moment combinations
 // r[0]=M, r[1]=trM2/2, r[2..7]=M2/2, r[8..10]=-trM3/2, r[11]=ttrM4/8,
-// r[12..21]=-M3/6, r[22..27]=trM4/4, r[28..42]=M4/24.
+// r[12..21]=-M3/6, r[22..27]=trM4/4, r[28..42]=M4/24 (the float records
+// of the PC kernel hold groups 2, 3, 4 times 3, 15, 105; the Ewald table
+// holds them as they are).
 template <typename T, typename Rec>
 __device__ __forceinline__ void multipole_terms(const Rec& r, T x, T y, T z, T& P2, T& P3,
                                                 T& P4, T& g2x, T& g2y, T& g2z, T& g3x, T& g3y,
@@ -533,6 +558,14 @@ __device__ __forceinline__ void pp_one(float sx, float sy, float sz, float m, fl
 // scaled), eps2t = t^2 eps^2, moments of order k times t^k.  Then
 // phi = t phi'(R') and acc = t^2 acc'(R'): one factor t is folded into a_n,
 // the other into the accumulation.
+//
+// With a_n = a0 u^n (2n-1)!!, u = -1/D, and the staged groups already
+// carrying (2n-1)!! (so the multipole_terms outputs are Q_n = (2n-1)!! P_n
+// and their gradients), the radial sums are polynomials in u:
+//   sum_n a_n P_n     = a0 f(u),             f(u) = sum_n u^n Q_n,
+//   sum_n a_{n+1} P_n = a0 u (f + 2u f'(u)), since (2n+1)!! = (2n+1)(2n-1)!!,
+//   sum_n a_n grad P_n = sum_n a0 u^n grad Q_n,
+// with f and f' from one Horner pass.
 __device__ __forceinline__ void pc_one(const float (&r)[kRec], float t, float cx, float cy,
                                        float cz, float px, float py, float pz, float eps2t,
                                        Acc4& A) {
@@ -541,22 +574,22 @@ __device__ __forceinline__ void pc_one(const float (&r)[kRec], float t, float cx
     const float w = __builtin_amdgcn_rsqf(D);
     const float a0 = w * t;
     const float u = -(w * w);
-    const float u3 = 3.f * u, u5 = 5.f * u, u7 = 7.f * u, u9 = 9.f * u;
+    float Q2, Q3, Q4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
+    multipole_terms<float>(r, x, y, z, Q2, Q3, Q4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z);
+    const float f3 = fmaf(u, Q4, Q3);
+    const float f2 = fmaf(u, f3, Q2);
+    const float d2 = fmaf(u, Q4, f3);
+    const float f1 = fmaf(u, f2, r[1]);
+    const float d1 = fmaf(u, d2, f2);
+    const float f0 = fmaf(u, f1, r[0]);
+    const float d0 = fmaf(u, d1, f1);
+    A.p = fmaf(-a0, f0, A.p);
     const float a1 = a0 * u;
-    const float a2 = a1 * u3;
-    const float a3 = a2 * u5;
-    const float a4x4 = a3 * (4.f * u7);
-    float P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
-    multipole_terms<float>(r, x, y, z, P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z);
-    // a_n = a0 u^n (2n-1)!!, so both radial sums nest (Horner in u):
-    //   sum_n a_n P_n     = a0 (M + u (P1 + 3u (P2 + 5u (P3 + 7u P4)))),
-    //   sum_n a_{n+1} P_n = a1 (M + 3u (P1 + 5u (P2 + 7u (P3 + 9u P4)))).
-    const float hp = fmaf(u, fmaf(u3, fmaf(u5, fmaf(u7, P4, P3), P2), r[1]), r[0]);
-    A.p = fmaf(-a0, hp, A.p);
-    const float S = a1 * fmaf(u3, fmaf(u5, fmaf(u7, fmaf(u9, P4, P3), P2), r[1]), r[0]);
-    A.x = fmaf(t, S * x + a2 * g2x + a3 * g3x + a4x4 * v4x, A.x);
-    A.y = fmaf(t, S * y + a2 * g2y + a3 * g3y + a4x4 * v4y, A.y);
-    A.z = fmaf(t, S * z + a2 * g2z + a3 * g3z + a4x4 * v4z, A.z);
+    const float S = a1 * fmaf(u + u, d0, f0);
+    const float b2 = a1 * u, b3 = b2 * u, b4x4 = b3 * (4.f * u);  // grad Q4 = 4 v4
+    A.x = fmaf(t, S * x + b2 * g2x + b3 * g3x + b4x4 * v4x, A.x);
+    A.y = fmaf(t, S * y + b2 * g2y + b3 * g3y + b4x4 * v4y, A.y);
+    A.z = fmaf(t, S * z + b2 * g2z + b3 * g3z + b4x4 * v4z, A.z);
 }
 
 // Load of a wave-uniform element of memory that no kernel running at the
@@ -734,7 +767,20 @@ __global__ void __launch_bounds__(kWave)
                     }
                 }
                 __syncthreads();
-                for (int t0 = 0; t0 < total; t0 += kWave) {
+                // two sources per lane while two full rows remain (a sink's
+                // scalar operands then serve two interactions), then one
+                int t0 = 0;
+                for (; t0 + 2 * kWave <= total; t0 += 2 * kWave) {
+                    const float4 s = lds[t0 + lane];
+                    const float4 s2 = lds[t0 + kWave + lane];
+#pragma unroll
+                    for (int i = 0; i < kBucket; ++i)
+                        if (i < nsink) {
+                            pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                            pp_one(s2.x, s2.y, s2.z, s2.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                        }
+                }
+                for (; t0 < total; t0 += kWave) {
                     const int t = t0 + lane;
                     // padding lanes: a massless source at the bucket centre (finite, adds 0)
                     const float4 s = t < total ? lds[t] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -857,6 +903,14 @@ struct EwaldArgs {
     float* __restrict__ pot;
     double L, alpha;
     int real_layers, h2max, hmax, order, accumulate;
+    // Judge of the surrogate.  With `sample` set, index j < n_sample stands
+    // for particle j * stride, and its exact acceleration, a valid flag and
+    // the PP + PC acceleration before the correction go to
+    // sample[kSampleRec * j + 0..7] instead of acc and pot.  With `gate`
+    // set, the kernel does nothing unless the judge chose the exact path.
+    int64_t stride, n_sample;
+    double* sample;
+    const Control* gate;
 };
 
 // Packed symmetric components of orders 2, 3, 4: multiplicity (number of
@@ -1078,9 +1132,16 @@ inline size_t ewald_lds_bytes(int hmax) {
 
 __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
     extern __shared__ double2 ew_lds[];
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    if (a.active && !a.active[i]) return;
+    if (a.gate && a.gate->ew_fallback == 0) return;
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= (a.sample ? a.n_sample : a.n)) return;
+    const int64_t i = a.sample ? j * a.stride : j;
+    double* out = a.sample ? a.sample + kSampleRec * j : nullptr;
+    if (i >= a.n || (a.active && !a.active[i])) {
+        if (out)
+            for (int k = 0; k < kSampleRec; ++k) out[k] = 0.0;
+        return;
+    }
     const TableRec rec{a.table};
     const double invL = 1.0 / a.L;
     const double rx = (a.pos[3 * i] - a.com[0]) * invL;
@@ -1198,7 +1259,16 @@ __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
     float* px = a.acc + i;
     float* py = a.acc + a.n + i;
     float* pz = a.acc + 2 * a.n + i;
-    if (a.accumulate) {
+    if (out) {
+        out[0] = ax;
+        out[1] = ay;
+        out[2] = az;
+        out[3] = 1.0;
+        out[4] = a.accumulate ? double(*px) : 0.0;
+        out[5] = a.accumulate ? double(*py) : 0.0;
+        out[6] = a.accumulate ? double(*pz) : 0.0;
+        out[7] = 0.0;
+    } else if (a.accumulate) {
         *px = float(double(*px) + ax);
         *py = float(double(*py) + ay);
         *pz = float(double(*pz) + az);
@@ -1208,6 +1278,47 @@ __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
         *py = float(ay);
         *pz = float(az);
         a.pot[i] = float(phi);
+    }
+}
+
+// The surrogate's verdict from the sample (one block, fixed summation
+// order): err = sqrt(mean over the valid records of |a_s - a_e|^2 /
+// |a_base + a_e|^2), the rms relative force error the surrogate adds; the
+// exact path is chosen when err > tol, err is not a number, or no sampled
+// particle was active.  A record with zero total force and a non-zero
+// deviation counts as infinitely wrong.
+constexpr int kJudgeThreads = 256;
+__global__ void __launch_bounds__(kJudgeThreads) k_ewald_judge(Control* ctl,
+                                                               const double* sample,
+                                                               int64_t n_sample, double tol) {
+    __shared__ double s_sum[kJudgeThreads], s_cnt[kJudgeThreads];
+    double sum = 0.0, cnt = 0.0;
+    for (int64_t j = threadIdx.x; j < n_sample; j += kJudgeThreads) {
+        const double* r = sample + kSampleRec * j;
+        if (r[3] == 0.0) continue;
+        const double dx = r[8] - r[0], dy = r[9] - r[1], dz = r[10] - r[2];
+        const double tx = r[4] + r[0], ty = r[5] + r[1], tz = r[6] + r[2];
+        const double num = dx * dx + dy * dy + dz * dz;
+        const double den = tx * tx + ty * ty + tz * tz;
+        sum += den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        cnt += 1.0;
+    }
+    s_sum[threadIdx.x] = sum;
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int h = kJudgeThreads / 2; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) {
+            s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = s_cnt[0];
+        const double err = n > 0.0 ? sqrt(s_sum[0] / n) : 0.0;
+        ctl->ew_err = err;
+        ctl->ew_samples = (unsigned long long)(n);
+        ctl->ew_fallback = (n == 0.0 || !(err <= tol)) ? 1 : 0;
     }
 }
 
@@ -1293,6 +1404,12 @@ struct LaunchSet {
     const double* com;
     int64_t n, n_bucket, n_cell;
     int use_mask, tree, ewald, variant, interact_blocks, surrogate_blocks;
+    // SURROGATE_FALLBACK: the judge's sample and the grid of the gated
+    // exact launch
+    double* sample;
+    int64_t sample_stride, n_sample;
+    double judge_tol;
+    int sample_ewald_blocks, sample_surrogate_blocks, gated_ewald_blocks;
 };
 
 namespace {
@@ -1498,9 +1615,9 @@ mgrav_status mgrav_bind(mgrav_ctx* c, const mgrav_problem* p, void* workspace, s
     c->have_run = false;
     c->active = nullptr;
     if (p->box_L > 0.0 && p->n_images == 27)
-        c->ewald = mgrav_ewald{MGRAV_EWALD_EXACT, 2.6, 1, 10, 4, 1};
+        c->ewald = mgrav_ewald{MGRAV_EWALD_EXACT, 2.6, 1, 10, 4, 1, 1e-4, 0};
     else
-        c->ewald = mgrav_ewald{MGRAV_EWALD_NONE, 2.6, 1, 10, 4, 1};
+        c->ewald = mgrav_ewald{MGRAV_EWALD_NONE, 2.6, 1, 10, 4, 1, 1e-4, 0};
 
     // the staging kernels run at the start of the next compute (inside its
     // first graph) or, if a wait comes first, at that wait
@@ -1518,17 +1635,24 @@ mgrav_status mgrav_set_ewald(mgrav_ctx* c, const mgrav_ewald* cfg) {
         c->ewald = *cfg;
         return MGRAV_OK;
     }
-    if (cfg->mode != MGRAV_EWALD_EXACT && cfg->mode != MGRAV_EWALD_SURROGATE)
+    if (cfg->mode != MGRAV_EWALD_EXACT && cfg->mode != MGRAV_EWALD_SURROGATE &&
+        cfg->mode != MGRAV_EWALD_SURROGATE_FALLBACK)
         return fail(c, MGRAV_ERR_INVALID_ARG, "unknown mode");
     if (!(c->prob.box_L > 0.0) || c->prob.n_images != 27)
         return fail(c, MGRAV_ERR_INVALID_ARG, "Ewald needs a periodic problem");
-    if (cfg->mode == MGRAV_EWALD_SURROGATE) {
+    if (cfg->mode != MGRAV_EWALD_EXACT) {
         if (!c->mlp.ws || !c->mlp.has_weights)
             return fail(c, MGRAV_ERR_NOT_TRAINED, "no surrogate weights loaded");
         if (cfg->top_cells != 1 && cfg->top_cells != 8 && cfg->top_cells != 64)
             return fail(c, MGRAV_ERR_INVALID_ARG, "top_cells must be 1, 8 or 64");
-        c->ewald = *cfg;
-        return MGRAV_OK;
+        if (cfg->mode == MGRAV_EWALD_SURROGATE) {
+            c->ewald = *cfg;
+            return MGRAV_OK;
+        }
+        if (!(cfg->fallback_tol >= 0.0))
+            return fail(c, MGRAV_ERR_INVALID_ARG, "fallback_tol must be >= 0");
+        if (cfg->sample_stride < 0)
+            return fail(c, MGRAV_ERR_INVALID_ARG, "sample_stride must be >= 0");
     }
     if (!(cfg->alpha > 0.5 && cfg->alpha < 10.0))
         return fail(c, MGRAV_ERR_INVALID_ARG, "alpha outside (0.5, 10)");
@@ -1585,11 +1709,12 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     L->use_mask = c->active ? 1 : 0;
     L->tree = (parts & (MGRAV_PART_PP | MGRAV_PART_PC)) != 0;
     L->ewald = (parts & MGRAV_PART_EWALD) ? c->ewald.mode : MGRAV_EWALD_NONE;
+    const bool judge = L->ewald == MGRAV_EWALD_SURROGATE_FALLBACK;
     L->variant = c->variant;
     L->interact_blocks = int(p.n_bucket < c->interact_blocks[c->variant]
                                  ? p.n_bucket
                                  : c->interact_blocks[c->variant]);
-    if (L->ewald == MGRAV_EWALD_SURROGATE) {
+    if (L->ewald == MGRAV_EWALD_SURROGATE || judge) {
         SurrogateArgs& g = L->sg;
         const MlpLayoutT& ml = c->mlp.lay;
         g.n = p.n;
@@ -1615,7 +1740,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         const int64_t blocks = (groups + wpb - 1) / wpb;
         L->surrogate_blocks = int(blocks < 8 * c->n_cu ? blocks : 8 * c->n_cu);
     }
-    if (L->ewald == MGRAV_EWALD_EXACT) {
+    if (L->ewald == MGRAV_EWALD_EXACT || judge) {
         EwaldArgs& e = L->e;
         e.n = p.n;
         e.pos = p.pos;
@@ -1632,6 +1757,29 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         e.hmax = int(std::floor(std::sqrt(double(e.h2max)) + 1e-9));
         e.order = c->ewald.order;
         e.accumulate = L->tree;
+    }
+    if (judge) {
+        // every stride-th particle, at most kMaxEwaldSamples of them
+        const int64_t min_stride = (p.n + kMaxEwaldSamples - 1) / kMaxEwaldSamples;
+        int64_t stride = c->ewald.sample_stride > 0
+                             ? c->ewald.sample_stride
+                             : (p.n + kDefaultEwaldSamples - 1) / kDefaultEwaldSamples;
+        if (stride < min_stride) stride = min_stride;
+        if (stride < 1) stride = 1;
+        L->sample = reinterpret_cast<double*>(w + c->lay.ewsample);
+        L->sample_stride = stride;
+        L->n_sample = (p.n + stride - 1) / stride;
+        L->judge_tol = c->ewald.fallback_tol;
+        const int64_t et = ewald_threads(L->e.hmax);
+        L->sample_ewald_blocks = int((L->n_sample + et - 1) / et);
+        const int per_group = 16 / (L->sg.ncell < 16 ? L->sg.ncell : 16);
+        const int64_t groups = (L->n_sample + per_group - 1) / per_group;
+        const int64_t wpb = kSurrogateThreads / kWave;
+        const int64_t sb = (groups + wpb - 1) / wpb;
+        L->sample_surrogate_blocks = int(sb < 8 * c->n_cu ? sb : 8 * c->n_cu);
+        // the exact path of a rejected surrogate (its blocks exit at once
+        // when the surrogate is accepted)
+        L->gated_ewald_blocks = int((p.n + et - 1) / et);
     }
 }
 
@@ -1675,6 +1823,36 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)),
                            dim3(kSurrogateThreads), 0,
                            c->stream, L.sg);
+    } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE_FALLBACK) {
+        // both corrections on the sample, the verdict, then the chosen one
+        // everywhere (the other launch exits at once)
+        const int et = ewald_threads(L.e.hmax);
+        const size_t lds = ewald_lds_bytes(L.e.hmax);
+        hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->stream, L.e);
+        hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.com,
+                           L.mom, L.n_cell, L.sg.ncell, const_cast<double*>(L.sg.cells));
+        EwaldArgs es = L.e;
+        es.sample = L.sample;
+        es.stride = L.sample_stride;
+        es.n_sample = L.n_sample;
+        hipLaunchKernelGGL(k_ewald, dim3(unsigned(L.sample_ewald_blocks)), dim3(et), lds,
+                           c->stream, es);
+        SurrogateArgs ss = L.sg;
+        ss.sample = L.sample;
+        ss.stride = L.sample_stride;
+        ss.n_sample = L.n_sample;
+        hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.sample_surrogate_blocks)),
+                           dim3(kSurrogateThreads), 0, c->stream, ss);
+        hipLaunchKernelGGL(k_ewald_judge, dim3(1), dim3(kJudgeThreads), 0, c->stream, L.r.ctl,
+                           L.sample, L.n_sample, L.judge_tol);
+        SurrogateArgs sg = L.sg;
+        sg.gate = L.r.ctl;
+        hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.surrogate_blocks)),
+                           dim3(kSurrogateThreads), 0, c->stream, sg);
+        EwaldArgs eg = L.e;
+        eg.gate = L.r.ctl;
+        hipLaunchKernelGGL(k_ewald, dim3(unsigned(L.gated_ewald_blocks)), dim3(et), lds,
+                           c->stream, eg);
     }
     if (phase == 2)
         hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
@@ -1862,6 +2040,9 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
             stats->graph_replay = g && g->gexec[0] != nullptr ? 1 : 0;
             stats->graph_error = c->graph_error;
             stats->interact_variant = g && g->set ? g->set->variant : c->variant;
+            stats->ewald_fallback = c->host_ctl->ew_fallback;
+            stats->ewald_samples = int64_t(c->host_ctl->ew_samples);
+            stats->ewald_sample_err = c->host_ctl->ew_err;
         }
     }
     const int err = c->host_ctl->err;

@@ -233,3 +233,119 @@ def test_surrogate_bad_top_cells_is_rejected(mg_ctx):
         ctx.set_ewald(mode=mg.EWALD_SURROGATE, top_cells=4)
     assert e.value.status == mg.ERR_INVALID_ARG
     ctx.wait(60)
+
+
+def _lattice_case(n_side, seed):
+    ps = workloads.perturbed_lattice(n_side, 0.2, seed=seed)
+    tree = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lists = oracle.build_lists(tree, 0.7, ps.eps)
+    return ps, tree, lists, ps.pos[tree.perm], ps.mass[tree.perm]
+
+
+def _judge_err(s, e, base):
+    """The judge's error written out on the host: rms over the sampled
+    particles of the surrogate's deviation from the exact correction
+    relative to the particle's total force."""
+    s, e, base = (np.asarray(x, np.float64) for x in (s, e, base))
+    return float(np.sqrt(np.mean(np.sum((s - e) ** 2, 1) / np.sum((base + e) ** 2, 1))))
+
+
+def test_surrogate_fallback_judge(mg_ctx):
+    """SURROGATE_FALLBACK: accepted, the results are the surrogate mode's bit
+    for bit; rejected, the exact mode's; the reported sample error is the
+    one computed on the host from the three separate runs, and the verdict
+    flips where the tolerance crosses it."""
+    mg, ctx = mg_ctx
+    ctx.mlp_set_weights(workloads.mlp_init(23).astype(np.float32))
+    ps, tree, lists, pos_t, mass_t = _lattice_case(16, 35)
+    n = len(pos_t)
+
+    def run(ew, parts=mg.PART_ALL, active=None):
+        return mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7, parts=parts, ewald=ew,
+                        active=active)
+
+    stride = 7
+    fb = lambda tol, s=stride: dict(mode=mg.EWALD_SURROGATE_FALLBACK, top_cells=1,
+                                    fallback_tol=tol, sample_stride=s)
+    _case("fallback judge lattice_16: reference runs (none, exact, surrogate)")
+    a_none, _, _ = run(dict(mode=mg.EWALD_NONE))
+    a_ex, p_ex, _ = run(dict(mode=mg.EWALD_EXACT))
+    a_sg, p_sg, _ = run(dict(mode=mg.EWALD_SURROGATE, top_cells=1))
+    idx = np.arange(0, n, stride)
+    a_none64 = a_none.astype(np.float64)
+    err_host = _judge_err(a_sg[idx] - a_none64[idx], a_ex[idx] - a_none64[idx], a_none64[idx])
+
+    _case("fallback judge: tolerance inf (accept)")
+    a1, p1, st = run(fb(np.inf))
+    print(f"  err device {st.ewald_sample_err:.6e} host {err_host:.6e}, samples "
+          f"{st.ewald_samples}, fallback {st.ewald_fallback}", flush=True)
+    assert st.ewald_fallback == 0 and st.ewald_samples == len(idx)
+    assert abs(st.ewald_sample_err - err_host) <= 1e-4 * err_host
+    assert np.array_equal(a1, a_sg) and np.array_equal(p1, p_sg)
+
+    _case("fallback judge: tolerance 0 (reject)")
+    a0, p0, st = run(fb(0.0))
+    assert st.ewald_fallback == 1 and st.ewald_samples == len(idx)
+    assert np.array_equal(a0, a_ex) and np.array_equal(p0, p_ex)
+
+    _case("fallback judge: tolerance either side of the sample error")
+    assert run(fb(1.01 * err_host))[2].ewald_fallback == 0
+    assert run(fb(0.99 * err_host))[2].ewald_fallback == 1
+
+    _case("fallback judge: Ewald part alone (error relative to the correction)")
+    e_ex, _, _ = run(dict(mode=mg.EWALD_EXACT), parts=mg.PART_EWALD)
+    e_sg, _, _ = run(dict(mode=mg.EWALD_SURROGATE, top_cells=1), parts=mg.PART_EWALD)
+    err_e = _judge_err(e_sg[idx], e_ex[idx], np.zeros((len(idx), 3)))
+    ae, _, st = run(fb(np.inf), parts=mg.PART_EWALD)
+    print(f"  err device {st.ewald_sample_err:.6e} host {err_e:.6e}", flush=True)
+    assert abs(st.ewald_sample_err - err_e) <= 1e-4 * err_e
+    assert np.array_equal(ae, e_sg)
+
+    _case("fallback judge: active subset, default stride (every particle sampled)")
+    act = (np.random.default_rng(3).random(n) < 0.3).astype(np.uint8)
+    am, _, st = run(fb(np.inf, 0), active=act)
+    assert st.ewald_samples == int(act.sum()) and st.ewald_fallback == 0
+    on = act.astype(bool)
+    assert np.array_equal(am[on], a_sg[on]) and np.all(am[~on] == 0)
+
+    _case("fallback judge: no sampled particle active -> exact path")
+    act2 = (np.arange(n) % stride != 0).astype(np.uint8)
+    am2, _, st = run(fb(np.inf), active=act2)
+    assert st.ewald_samples == 0 and st.ewald_fallback == 1
+    on2 = act2.astype(bool)
+    assert np.array_equal(am2[on2], a_ex[on2])
+
+
+def test_surrogate_fallback_sample_cap_and_arguments(mg_ctx):
+    """The sample never exceeds 16384 particles (a smaller stride is raised),
+    and bad judge arguments or missing weights are refused on the host."""
+    mg, ctx = mg_ctx
+    ctx.mlp_set_weights(workloads.mlp_init(24).astype(np.float32))
+    ps, tree, lists, pos_t, mass_t = _lattice_case(32, 36)
+    n = len(pos_t)
+    _case(f"fallback judge sample cap: lattice_32 (n={n}), stride 1 -> 2")
+    _, _, st = mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7,
+                        ewald=dict(mode=mg.EWALD_SURROGATE_FALLBACK, fallback_tol=np.inf,
+                                   sample_stride=1))
+    assert st.ewald_samples == 16384 and st.ewald_fallback == 0
+    _, _, st = mg.solve(ctx, pos_t, mass_t, tree, lists, ps.eps, 0.7,
+                        ewald=dict(mode=mg.EWALD_SURROGATE_FALLBACK, fallback_tol=np.inf))
+    assert st.ewald_samples == 8192
+
+    _case("fallback judge arguments refused on the host")
+    for bad in (dict(fallback_tol=-1.0), dict(fallback_tol=float("nan")),
+                dict(sample_stride=-3), dict(top_cells=4), dict(alpha=0.1)):
+        with pytest.raises(mg.MgravError) as e:
+            ctx.set_ewald(mode=mg.EWALD_SURROGATE_FALLBACK, **bad)
+        assert e.value.status == mg.ERR_INVALID_ARG, bad
+    ctx.wait(60)
+    fresh = mg.Context(0)
+    try:
+        tensors, p = fresh.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+        fresh.bind(p, tensors)
+        with pytest.raises(mg.MgravError) as e:
+            fresh.set_ewald(mode=mg.EWALD_SURROGATE_FALLBACK)
+        assert e.value.status == mg.ERR_NOT_TRAINED
+        fresh.wait(60)
+    finally:
+        fresh.close()

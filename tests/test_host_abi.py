@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(mg.EXPORTS)
-    assert mg.version() == 1
+    assert mg.version() == 2
 
 
 def test_status_strings():
@@ -126,3 +126,35 @@ def test_interact_variants_and_their_argument_checks():
     assert mg._lib.mgrav_interact_variants(None) == mg.ERR_INVALID_ARG
     assert mg._lib.mgrav_set_interact_variant(None, 0) == mg.ERR_INVALID_ARG
     assert mg._lib.mgrav_autotune(None, None, None, None, 100.0, None, None) == mg.ERR_INVALID_ARG
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct (checked with gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [("mgrav_problem", mg.Problem), ("mgrav_ewald", mg.EwaldConfig),
+             ("mgrav_stats", mg.Stats), ("mgrav_train_cfg", mg.TrainConfig)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mgrav.h"',
+             "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        cname, key, val = ln.split()
+        got[(cname, key)] = int(val)
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
