@@ -87,7 +87,16 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
-    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, total;
+    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, cinfo, total;
+};
+
+// Per cell, written first by the staging: the bounding-box centre and, for
+// a cell that is a valid bucket (a leaf with 1..16 particles inside [0, n)),
+// its particle range (count 0 otherwise).  The particle and PP staging
+// then read one record per cell instead of four arrays.
+struct CellInfo {
+    double cx, cy, cz;
+    int first, count;
 };
 
 // Sample of the surrogate judge: at most kMaxEwaldSamples particles, one
@@ -118,6 +127,8 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(double) * (64 + 8 * kMaxHalfK));
     l.ewsample = o;
     o += align256(sizeof(double) * kSampleRec * kMaxEwaldSamples);
+    l.cinfo = o;
+    o += align256(sizeof(CellInfo) * n_cell);
     l.total = o;
     return l;
 }
@@ -147,6 +158,7 @@ struct StageArgs {
     BucketWork* work;
     float* cellrec;
     float4* ppent;
+    CellInfo* cinfo;
 };
 
 // The control block (counters, error bits) into pinned host memory: the
@@ -170,20 +182,22 @@ __global__ void k_init_control(Control* ctl) {
     }
 }
 
-// Is cell c a valid bucket (leaf with 1..16 particles inside [0, n))?
-__device__ bool valid_bucket(const StageArgs& a, int64_t c, int64_t* first, int* cnt) {
-    if (c < 0 || c >= a.n_cell) return false;
-    if (a.child[2 * c] >= 0) return false;
+// (0) cells: bounding-box centre and, for a valid bucket (a leaf with
+// 1..16 particles inside [0, n)), its particle range.
+__global__ void k_stage_cellinfo(StageArgs a) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= a.n_cell) return;
+    const double* bb = a.bbox + 6 * c;
+    CellInfo ci;
+    ci.cx = 0.5 * (bb[0] + bb[3]);
+    ci.cy = 0.5 * (bb[1] + bb[4]);
+    ci.cz = 0.5 * (bb[2] + bb[5]);
     const int64_t f = a.cell_first[c];
     const int k = a.cell_count[c];
-    if (k < 1 || k > kBucket || f < 0 || f + k > a.n) return false;
-    *first = f;
-    *cnt = k;
-    return true;
-}
-
-__device__ void bbox_centre(const double* __restrict__ bbox, int64_t c, double C[3]) {
-    for (int d = 0; d < 3; ++d) C[d] = 0.5 * (bbox[6 * c + d] + bbox[6 * c + 3 + d]);
+    const bool ok = a.child[2 * c] < 0 && k >= 1 && k <= kBucket && f >= 0 && f + k <= a.n;
+    ci.first = ok ? int(f) : 0;
+    ci.count = ok ? k : 0;
+    a.cinfo[c] = ci;
 }
 
 // (1) particles: float offset from the bucket's bounding-box centre + mass.
@@ -193,9 +207,8 @@ __global__ void k_stage_particles(StageArgs a) {
     const int k = int(t % kBucket);
     if (b >= a.n_bucket) return;
     const int64_t c = a.bucket_cell[b];
-    int64_t first = 0;
-    int cnt = 0;
-    if (!valid_bucket(a, c, &first, &cnt)) {
+    const CellInfo ci = c >= 0 && c < a.n_cell ? a.cinfo[c] : CellInfo{0.0, 0.0, 0.0, 0, 0};
+    if (ci.count == 0) {
         if (k == 0) {
             atomicOr(&a.ctl->err, kErrTree);
             a.work[b].first = 0;
@@ -203,19 +216,17 @@ __global__ void k_stage_particles(StageArgs a) {
         }
         return;
     }
-    double C[3];
-    bbox_centre(a.bbox, c, C);
-    if (k < cnt) {
-        const int64_t p = first + k;
+    if (k < ci.count) {
+        const int64_t p = ci.first + k;
         const double x = a.pos[3 * p], y = a.pos[3 * p + 1], z = a.pos[3 * p + 2];
         const double m = a.mass[p];
         if (!(isfinite(x) && isfinite(y) && isfinite(z) && m > 0.0 && isfinite(m)))
             atomicOr(&a.ctl->err, kErrParticle);
-        a.pdat[p] = make_float4(float(x - C[0]), float(y - C[1]), float(z - C[2]), float(m));
+        a.pdat[p] = make_float4(float(x - ci.cx), float(y - ci.cy), float(z - ci.cz), float(m));
     }
     if (k == 0) {
-        a.work[b].first = int(first);
-        a.work[b].nsink = cnt;
+        a.work[b].first = ci.first;
+        a.work[b].nsink = ci.count;
     }
 }
 
@@ -243,7 +254,8 @@ __device__ float cell_inv_unit(const StageArgs& a, int64_t c) {
 
 // (2) cells: float coefficients of the order-4 expansion (multipole_terms,
 // pc_one), the order-k ones in units of the cell's length unit (times t^k),
-// and t = 1 / unit in the last word.
+// and t = 1 / unit in the last word.  (Staging the moments and records
+// through LDS for contiguous access measured slower: too few waves per CU.)
 __global__ void k_stage_cells(StageArgs a) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
@@ -281,60 +293,82 @@ __global__ void k_stage_cells(StageArgs a) {
                              float(r[4 * i + 3]));
 }
 
-__device__ inline int block_or(int v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
-    return v;
-}
-__device__ inline int block_sum(int v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // (3) PP entries: offset between the source bucket's centre (plus image
 // shift) and the sink bucket's centre, in double, rounded to float; the
 // source's first particle and count packed into the fourth word.  Also
 // checks the bucket's PC range; the PC entries themselves are read, checked
-// and turned into offsets by the interact kernel.
-__global__ void __launch_bounds__(kWave) k_stage_pp(StageArgs a) {
-    const int64_t b = blockIdx.x;
-    const int lane = threadIdx.x;
+// and turned into offsets by the interact kernel.  16 lanes per sink bucket
+// (4 buckets per wave), so that each wave keeps more list entries in flight.
+constexpr int kStagePPLanes = 16;
+constexpr int kStagePPRound = 4;
+__device__ inline int group_or(int v) {
+    for (int o = kStagePPLanes / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+__device__ inline int group_sum(int v) {
+    for (int o = kStagePPLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__global__ void __launch_bounds__(256) k_stage_pp(StageArgs a) {
+    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStagePPLanes;
+    const int sl = int(threadIdx.x % kStagePPLanes);
+    if (b >= a.n_bucket) return;  // whole groups: n_bucket * 16 threads are all in range
     const int64_t s = a.bucket_cell[b];
     const bool sink_ok = s >= 0 && s < a.n_cell;
     const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
     const bool range_ok = e0 >= 0 && e0 <= e1 && e1 <= a.n_pp;
     double C[3] = {0, 0, 0};
-    if (sink_ok) bbox_centre(a.bbox, s, C);
+    if (sink_ok) {
+        const CellInfo ci = a.cinfo[s];
+        C[0] = ci.cx;
+        C[1] = ci.cy;
+        C[2] = ci.cz;
+    }
     int nsrc = 0, self = 0, bad = 0;
     if (!range_ok || !sink_ok) bad = 1;
     if (range_ok) {
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
-            const int64_t src = a.pp_src[e];
-            const int img = a.pp_img[e];
-            int64_t f = 0;
-            int k = 0;
-            float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
-            if (sink_ok && img < a.n_images && valid_bucket(a, src, &f, &k)) {
-                double S[3];
-                bbox_centre(a.bbox, src, S);
-                out.x = float(S[0] + c_shift[img][0] * a.L - C[0]);
-                out.y = float(S[1] + c_shift[img][1] * a.L - C[1]);
-                out.z = float(S[2] + c_shift[img][2] * a.L - C[2]);
-                out.w = __uint_as_float(uint32_t(f) | (uint32_t(k) << 27));
-                nsrc += k;
-                if (src == s && img == 0) self = 1;
-            } else {
-                bad = 1;
+        // kStagePPRound entries per lane per round: all their loads, then all
+        // their cell records, are in flight together
+        for (int64_t eb = e0 + sl; eb < e1; eb += kStagePPRound * kStagePPLanes) {
+            int64_t src[kStagePPRound];
+            int img[kStagePPRound];
+#pragma unroll
+            for (int u = 0; u < kStagePPRound; ++u) {
+                const int64_t e = eb + u * kStagePPLanes;
+                src[u] = e < e1 ? int64_t(a.pp_src[e]) : -1;
+                img[u] = e < e1 ? int(a.pp_img[e]) : 0;
             }
-            a.ppent[e] = out;
+            CellInfo si[kStagePPRound];
+#pragma unroll
+            for (int u = 0; u < kStagePPRound; ++u)
+                si[u] = src[u] >= 0 && src[u] < a.n_cell ? a.cinfo[src[u]]
+                                                         : CellInfo{0.0, 0.0, 0.0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < kStagePPRound; ++u) {
+                const int64_t e = eb + u * kStagePPLanes;
+                if (e >= e1) continue;
+                float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
+                if (sink_ok && img[u] < a.n_images && si[u].count > 0) {
+                    out.x = float(si[u].cx + c_shift[img[u]][0] * a.L - C[0]);
+                    out.y = float(si[u].cy + c_shift[img[u]][1] * a.L - C[1]);
+                    out.z = float(si[u].cz + c_shift[img[u]][2] * a.L - C[2]);
+                    out.w = __uint_as_float(uint32_t(si[u].first) | (uint32_t(si[u].count) << 27));
+                    nsrc += si[u].count;
+                    if (src[u] == s && img[u] == 0) self = 1;
+                } else {
+                    bad = 1;
+                }
+                a.ppent[e] = out;
+            }
         }
     }
     const int64_t g0 = a.pc_off[b], g1 = a.pc_off[b + 1];
     const bool pc_ok = g0 >= 0 && g0 <= g1 && g1 <= a.n_pc;
     if (!pc_ok) bad = 1;
-    bad = block_or(bad);
-    self = block_or(self);
-    nsrc = block_sum(nsrc);
-    if (lane == 0) {
+    bad = group_or(bad);
+    self = group_or(self);
+    nsrc = group_sum(nsrc);
+    if (sl == 0) {
         if (bad) atomicOr(&a.ctl->err, kErrList);
         a.work[b].self = self;
         a.work[b].nsrc = nsrc;
@@ -390,9 +424,11 @@ __global__ void __launch_bounds__(256) k_select(RunArgs a) {
     __shared__ int hist[kCostBins];
     if (threadIdx.x < kCostBins) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     unsigned long long npp = 0, npc = 0, nact = 0, nb = 0;
-    if (b < a.n_bucket) {
+    // grid-stride over the buckets: a bounded grid keeps the number of
+    // same-address atomics (one set per block) small
+    for (int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < a.n_bucket;
+         b += int64_t(gridDim.x) * blockDim.x) {
         const BucketWork wk = a.work[b];
         int na = wk.nsink;
         if (a.active) {
@@ -410,10 +446,10 @@ __global__ void __launch_bounds__(256) k_select(RunArgs a) {
         }
         a.bins[b] = (signed char)bin;
         if (na > 0) {
-            nact = na;
-            nb = 1;
-            npp = (unsigned long long)na * (unsigned long long)wk.nsrc;
-            npc = (unsigned long long)na * (unsigned long long)(wk.pc1 - wk.pc0);
+            nact += na;
+            nb += 1;
+            npp += (unsigned long long)na * (unsigned long long)wk.nsrc;
+            npc += (unsigned long long)na * (unsigned long long)(wk.pc1 - wk.pc0);
         }
     }
     // block reduction, one atomic per block
@@ -461,7 +497,8 @@ __global__ void k_order_scan(Control* ctl) {
 
 // Block-aggregated scatter: one global atomic per (block, bin) reserves a
 // range of queue slots; ranks inside the block come from LDS atomics.
-__global__ void __launch_bounds__(256) k_order_scatter(RunArgs a) {
+constexpr int kScatterThreads = 1024;
+__global__ void __launch_bounds__(kScatterThreads) k_order_scatter(RunArgs a) {
     __shared__ int cnt[kCostBins];
     __shared__ int base[kCostBins];
     if (threadIdx.x < kCostBins) cnt[threadIdx.x] = 0;
@@ -1478,6 +1515,7 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.work = reinterpret_cast<BucketWork*>(w + c->lay.work);
     a.cellrec = reinterpret_cast<float*>(w + c->lay.cellrec);
     a.ppent = reinterpret_cast<float4*>(w + c->lay.ppent);
+    a.cinfo = reinterpret_cast<CellInfo*>(w + c->lay.cinfo);
     return a;
 }
 
@@ -1794,22 +1832,27 @@ static bool phase_used(const LaunchSet& L, int phase) {
 // The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
 static void enqueue_stage(hipStream_t st, const StageArgs& a) {
     hipLaunchKernelGGL(k_init_control, dim3(1), dim3(kWave), 0, st, a.ctl);
+    hipLaunchKernelGGL(k_stage_cellinfo, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0,
+                       st, a);
     const int64_t nt = a.n_bucket * kBucket;
     hipLaunchKernelGGL(k_stage_particles, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0, st,
                        a);
-    hipLaunchKernelGGL(k_stage_pp, dim3(unsigned(a.n_bucket)), dim3(kWave), 0, st, a);
+    const int64_t np = a.n_bucket * kStagePPLanes;
+    hipLaunchKernelGGL(k_stage_pp, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, a);
 }
 
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     if (phase == 0) {
         if (L.stage) enqueue_stage(c->stream, L.s);
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
-        hipLaunchKernelGGL(k_select, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256), 0,
-                           c->stream, L.r);
+        const int64_t sel = (L.n_bucket + 255) / 256;
+        hipLaunchKernelGGL(k_select, dim3(unsigned(sel < 4 * c->n_cu ? sel : 4 * c->n_cu)),
+                           dim3(256), 0, c->stream, L.r);
         hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
-        hipLaunchKernelGGL(k_order_scatter, dim3(unsigned((L.n_bucket + 255) / 256)), dim3(256),
-                           0, c->stream, L.r);
+        hipLaunchKernelGGL(k_order_scatter,
+                           dim3(unsigned((L.n_bucket + kScatterThreads - 1) / kScatterThreads)),
+                           dim3(kScatterThreads), 0, c->stream, L.r);
     } else if (phase == 1 && L.tree) {
         launch_interact(L.variant, dim3(unsigned(L.interact_blocks)), c->stream, L.r);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {

@@ -95,7 +95,7 @@ def test_workspace_size_validates_problem():
               "bucket_cell", "pp_off", "pp_src", "pp_img", "pc_off", "pc_src", "pc_img"):
         setattr(p, f, 4096)
     assert mg._lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == mg.OK
-    assert sz.value >= 1000 * 16 + 127 * 176 + 500 * 16  # particles, cell records, PP entries
+    assert sz.value >= 1000 * 16 + 127 * (176 + 32) + 500 * 16  # particles, cells, PP entries
     p.eps = 0.0
     assert mg._lib.mgrav_workspace_size(ctypes.byref(p), ctypes.byref(sz)) == mg.ERR_INVALID_ARG
     p.eps, p.n_images = 0.01, 27  # periodic images without a box
