@@ -254,8 +254,9 @@ __device__ float cell_inv_unit(const StageArgs& a, int64_t c) {
 
 // (2) cells: float coefficients of the order-4 expansion (multipole_terms,
 // pc_one), the order-k ones in units of the cell's length unit (times t^k),
-// and t = 1 / unit in the last word.  (Staging the moments and records
-// through LDS for contiguous access measured slower: too few waves per CU.)
+// and t = 1 / unit in the last word.  (Staging moments and records through
+// LDS for contiguous access, or four lanes per cell each storing a quarter,
+// measured slower.)
 __global__ void k_stage_cells(StageArgs a) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
@@ -297,9 +298,9 @@ __global__ void k_stage_cells(StageArgs a) {
 // shift) and the sink bucket's centre, in double, rounded to float; the
 // source's first particle and count packed into the fourth word.  Also
 // checks the bucket's PC range; the PC entries themselves are read, checked
-// and turned into offsets by the interact kernel.  16 lanes per sink bucket
-// (4 buckets per wave), so that each wave keeps more list entries in flight.
-constexpr int kStagePPLanes = 16;
+// and turned into offsets by the interact kernel.  8 lanes per sink bucket
+// (8 buckets per wave), so that each wave keeps more list entries in flight.
+constexpr int kStagePPLanes = 8;
 constexpr int kStagePPRound = 4;
 __device__ inline int group_or(int v) {
     for (int o = kStagePPLanes / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
@@ -312,7 +313,7 @@ __device__ inline int group_sum(int v) {
 __global__ void __launch_bounds__(256) k_stage_pp(StageArgs a) {
     const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStagePPLanes;
     const int sl = int(threadIdx.x % kStagePPLanes);
-    if (b >= a.n_bucket) return;  // whole groups: n_bucket * 16 threads are all in range
+    if (b >= a.n_bucket) return;  // whole groups: the first n_bucket groups are in range
     const int64_t s = a.bucket_cell[b];
     const bool sink_ok = s >= 0 && s < a.n_cell;
     const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
