@@ -63,6 +63,7 @@ struct Control {
     unsigned long long ew_samples;  // surrogate judge: active particles sampled
     int ew_fallback;                // surrogate judge: 1 = exact path taken
     int ew_pad;
+    unsigned long long n_list;      // active particles listed by k_select (mask set)
 };
 
 // Image shifts in units of L: id 0 the box, 1..26 lexicographic {-1,0,1}^3.
@@ -87,7 +88,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
-    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, cinfo, total;
+    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, cinfo, plist, total;
 };
 
 // Per cell, written first by the staging: the bounding-box centre and, for
@@ -129,6 +130,8 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(double) * kSampleRec * kMaxEwaldSamples);
     l.cinfo = o;
     o += align256(sizeof(CellInfo) * n_cell);
+    l.plist = o;
+    o += align256(sizeof(int) * n);
     l.total = o;
     return l;
 }
@@ -179,6 +182,7 @@ __global__ void k_init_control(Control* ctl) {
         ctl->ew_err = 0.0;
         ctl->ew_samples = 0;
         ctl->ew_fallback = 0;
+        ctl->n_list = 0;
     }
 }
 
@@ -405,6 +409,7 @@ struct RunArgs {
     float* __restrict__ pot;  // [n]
     float eps2;
     int parts;
+    int* plist;  // with a mask: the active particles, for the Ewald kernels
 };
 
 __global__ void k_reset(Control* ctl) {
@@ -415,54 +420,90 @@ __global__ void k_reset(Control* ctl) {
         ctl->ew_err = 0.0;
         ctl->ew_samples = 0;
         ctl->ew_fallback = 0;
+        ctl->n_list = 0;
     }
     if (threadIdx.x < kCostBins) ctl->bin_count[threadIdx.x] = 0;
 }
 
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
 // Active buckets into the work queue (in bucket order when all particles
-// are active) and the interaction counts of the active sinks.
-__global__ void __launch_bounds__(256) k_select(RunArgs a) {
+// are active) and the interaction counts of the active sinks.  With a mask,
+// also the list of active particles (block-aggregated appends; the order
+// of blocks in it is not fixed, and nothing depends on it).
+constexpr int kSelectThreads = 256;
+__global__ void __launch_bounds__(kSelectThreads) k_select(RunArgs a) {
     __shared__ int hist[kCostBins];
+    __shared__ int wsum[kSelectThreads / kWave];
+    __shared__ unsigned long long lbase;
     if (threadIdx.x < kCostBins) hist[threadIdx.x] = 0;
     __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     unsigned long long npp = 0, npc = 0, nact = 0, nb = 0;
-    // grid-stride over the buckets: a bounded grid keeps the number of
-    // same-address atomics (one set per block) small
-    for (int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < a.n_bucket;
-         b += int64_t(gridDim.x) * blockDim.x) {
-        const BucketWork wk = a.work[b];
-        int na = wk.nsink;
-        if (a.active) {
-            na = 0;
-            for (int k = 0; k < wk.nsink; ++k) na += a.active[wk.first + k] != 0;
+    // grid-stride over the buckets (the same trip count for the whole
+    // block): a bounded grid keeps the same-address atomics few
+    for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < a.n_bucket;
+         b0 += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t b = b0 + threadIdx.x;
+        BucketWork wk{};
+        int na = 0;
+        if (b < a.n_bucket) {
+            wk = a.work[b];
+            na = wk.nsink;
+            if (a.active) {
+                na = 0;
+                for (int k = 0; k < wk.nsink; ++k) na += a.active[wk.first + k] != 0;
+            }
+            int bin = -1;
+            if (na > 0) {
+                // work of the bucket in FLOP, binned by its base-2 logarithm
+                const unsigned long long cost =
+                    (unsigned long long)wk.nsink *
+                    ((unsigned long long)wk.nsrc * 20ull +
+                     (unsigned long long)(wk.pc1 - wk.pc0) * 242ull);
+                bin = 63 - __clzll(cost | 1ull);
+                atomicAdd(&hist[bin], 1);
+            }
+            a.bins[b] = (signed char)bin;
+            if (na > 0) {
+                nact += na;
+                nb += 1;
+                npp += (unsigned long long)na * (unsigned long long)wk.nsrc;
+                npc += (unsigned long long)na * (unsigned long long)(wk.pc1 - wk.pc0);
+            }
         }
-        int bin = -1;
-        if (na > 0) {
-            // work of the bucket in FLOP, binned by its base-2 logarithm
-            const unsigned long long cost =
-                (unsigned long long)wk.nsink *
-                ((unsigned long long)wk.nsrc * 20ull + (unsigned long long)(wk.pc1 - wk.pc0) * 242ull);
-            bin = 63 - __clzll(cost | 1ull);
-            atomicAdd(&hist[bin], 1);
-        }
-        a.bins[b] = (signed char)bin;
-        if (na > 0) {
-            nact += na;
-            nb += 1;
-            npp += (unsigned long long)na * (unsigned long long)wk.nsrc;
-            npc += (unsigned long long)na * (unsigned long long)(wk.pc1 - wk.pc0);
+        if (a.plist) {  // append this block's active particles
+            const int incl = wave_incl_scan(na, lane);
+            if (lane == kWave - 1) wsum[w] = incl;
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int q = 0; q < kSelectThreads / kWave; ++q) {
+                before += q < w ? wsum[q] : 0;
+                total += wsum[q];
+            }
+            if (threadIdx.x == 0) lbase = atomicAdd(&a.ctl->n_list, (unsigned long long)total);
+            __syncthreads();
+            int64_t slot = int64_t(lbase) + before + incl - na;
+            for (int k = 0; k < wk.nsink && na > 0; ++k)
+                if (a.active[wk.first + k]) a.plist[slot++] = wk.first + k;
+            __syncthreads();  // wsum and lbase are rewritten by the next round
         }
     }
     // block reduction, one atomic per block
-    __shared__ unsigned long long red[4][256 / kWave];
+    __shared__ unsigned long long red[4][kSelectThreads / kWave];
     for (int o = kWave / 2; o > 0; o >>= 1) {
         npp += __shfl_xor(npp, o);
         npc += __shfl_xor(npc, o);
         nact += __shfl_xor(nact, o);
         nb += __shfl_xor(nb, o);
     }
-    const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (lane == 0) {
         red[0][w] = npp;
         red[1][w] = npc;
         red[2][w] = nact;
@@ -473,7 +514,7 @@ __global__ void __launch_bounds__(256) k_select(RunArgs a) {
         atomicAdd(&a.ctl->bin_count[threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 0) {
         unsigned long long s[4] = {0, 0, 0, 0};
-        for (int i = 0; i < int(blockDim.x / kWave); ++i)
+        for (int i = 0; i < kSelectThreads / kWave; ++i)
             for (int q = 0; q < 4; ++q) s[q] += red[q][i];
         if (s[2]) {
             atomicAdd(&a.ctl->n_pp_int, s[0]);
@@ -687,14 +728,6 @@ __device__ __forceinline__ void load_pc(const RunArgs& a, int64_t f, int64_t f1,
 #pragma unroll
         for (int i = 0; i < kRec; ++i) r[i] = 0.f;
     }
-}
-
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
-    return v;
 }
 
 // Persistent PP + PC kernel.  One wavefront per work item (a sink bucket
@@ -949,6 +982,10 @@ struct EwaldArgs {
     int64_t stride, n_sample;
     double* sample;
     const Control* gate;
+    // With `list` set (a mask is in use): the particles are list[j] for
+    // j < ctl->n_list, taken by a grid-stride loop over a bounded grid.
+    const int* list;
+    const Control* ctl;
 };
 
 // Packed symmetric components of orders 2, 3, 4: multiplicity (number of
@@ -1168,18 +1205,10 @@ inline size_t ewald_lds_bytes(int hmax) {
     return sizeof(double2) * size_t(hmax + 1 + 2 * (2 * hmax + 1)) * size_t(ewald_threads(hmax));
 }
 
-__global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
-    extern __shared__ double2 ew_lds[];
-    if (a.gate && a.gate->ew_fallback == 0) return;
-    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j >= (a.sample ? a.n_sample : a.n)) return;
-    const int64_t i = a.sample ? j * a.stride : j;
-    double* out = a.sample ? a.sample + kSampleRec * j : nullptr;
-    if (i >= a.n || (a.active && !a.active[i])) {
-        if (out)
-            for (int k = 0; k < kSampleRec; ++k) out[k] = 0.0;
-        return;
-    }
+// The correction at particle i into acc and pot, or into the judge's
+// sample record `out`.
+__device__ __forceinline__ void ewald_particle(const EwaldArgs& a, int64_t i, double* out,
+                                               double2* ew_lds) {
     const TableRec rec{a.table};
     const double invL = 1.0 / a.L;
     const double rx = (a.pos[3 * i] - a.com[0]) * invL;
@@ -1319,6 +1348,35 @@ __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
     }
 }
 
+// One thread per particle (or per sampled particle of the judge).
+__global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
+    extern __shared__ double2 ew_lds[];
+    if (a.gate && a.gate->ew_fallback == 0) return;
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= (a.sample ? a.n_sample : a.n)) return;
+    const int64_t i = a.sample ? j * a.stride : j;
+    double* out = a.sample ? a.sample + kSampleRec * j : nullptr;
+    if (i >= a.n || (a.active && !a.active[i])) {
+        if (out)
+            for (int k = 0; k < kSampleRec; ++k) out[k] = 0.0;
+        return;
+    }
+    ewald_particle(a, i, out, ew_lds);
+}
+
+// The listed active particles (a mask is in use), over a bounded grid: a
+// grid covering every particle would spend most of its time starting
+// blocks that exit, each holding its LDS tables while it does.
+__global__ void __launch_bounds__(kEwaldThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_ewald_list(EwaldArgs a) {
+    extern __shared__ double2 ew_lds[];
+    if (a.gate && a.gate->ew_fallback == 0) return;
+    const int64_t count = int64_t(a.ctl->n_list);
+    for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < count;
+         j += int64_t(gridDim.x) * blockDim.x)
+        ewald_particle(a, a.list[j], nullptr, ew_lds);
+}
+
 // The surrogate's verdict from the sample (one block, fixed summation
 // order): err = sqrt(mean over the valid records of |a_s - a_e|^2 /
 // |a_base + a_e|^2), the rms relative force error the surrogate adds; the
@@ -1442,12 +1500,11 @@ struct LaunchSet {
     const double* com;
     int64_t n, n_bucket, n_cell;
     int use_mask, tree, ewald, variant, interact_blocks, surrogate_blocks;
-    // SURROGATE_FALLBACK: the judge's sample and the grid of the gated
-    // exact launch
+    // SURROGATE_FALLBACK: the judge's sample
     double* sample;
     int64_t sample_stride, n_sample;
     double judge_tol;
-    int sample_ewald_blocks, sample_surrogate_blocks, gated_ewald_blocks;
+    int sample_ewald_blocks, sample_surrogate_blocks;
 };
 
 namespace {
@@ -1743,6 +1800,8 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     r.pot = pot;
     r.eps2 = float(p.eps * p.eps);
     r.parts = parts;
+    int* plist = c->active ? reinterpret_cast<int*>(w + c->lay.plist) : nullptr;
+    r.plist = plist;
     L->n = p.n;
     L->n_bucket = p.n_bucket;
     L->use_mask = c->active ? 1 : 0;
@@ -1769,6 +1828,8 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         g.acc = acc;
         g.pot = pot;
         g.accumulate = L->tree;
+        g.list = plist;
+        g.ctl = r.ctl;
         L->child = p.child;
         L->mom = p.mom;
         L->com = p.com;
@@ -1796,6 +1857,8 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         e.hmax = int(std::floor(std::sqrt(double(e.h2max)) + 1e-9));
         e.order = c->ewald.order;
         e.accumulate = L->tree;
+        e.list = plist;
+        e.ctl = r.ctl;
     }
     if (judge) {
         // every stride-th particle, at most kMaxEwaldSamples of them
@@ -1816,9 +1879,6 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         const int64_t wpb = kSurrogateThreads / kWave;
         const int64_t sb = (groups + wpb - 1) / wpb;
         L->sample_surrogate_blocks = int(sb < 8 * c->n_cu ? sb : 8 * c->n_cu);
-        // the exact path of a rejected surrogate (its blocks exit at once
-        // when the surrogate is accepted)
-        L->gated_ewald_blocks = int((p.n + et - 1) / et);
     }
 }
 
@@ -1843,6 +1903,21 @@ static void enqueue_stage(hipStream_t st, const StageArgs& a) {
     hipLaunchKernelGGL(k_stage_pp, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, a);
 }
 
+// Exact correction of every active particle: one thread per particle, or,
+// with a mask, a bounded grid over the list of active particles.
+static void launch_ewald_all(mgrav_ctx* c, const LaunchSet& L, const EwaldArgs& e) {
+    const int et = ewald_threads(e.hmax);
+    const size_t lds = ewald_lds_bytes(e.hmax);
+    const int64_t nb = (L.n + et - 1) / et;
+    if (e.list) {
+        const int64_t cap = 16 * int64_t(c->n_cu);
+        hipLaunchKernelGGL(k_ewald_list, dim3(unsigned(nb < cap ? nb : cap)), dim3(et), lds,
+                           c->stream, e);
+    } else {
+        hipLaunchKernelGGL(k_ewald, dim3(unsigned(nb)), dim3(et), lds, c->stream, e);
+    }
+}
+
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     if (phase == 0) {
         if (L.stage) enqueue_stage(c->stream, L.s);
@@ -1858,9 +1933,7 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         launch_interact(L.variant, dim3(unsigned(L.interact_blocks)), c->stream, L.r);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {
         hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->stream, L.e);
-        const int et = ewald_threads(L.e.hmax);
-        hipLaunchKernelGGL(k_ewald, dim3(unsigned((L.n + et - 1) / et)), dim3(et),
-                           ewald_lds_bytes(L.e.hmax), c->stream, L.e);
+        launch_ewald_all(c, L, L.e);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE) {
         hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.com,
                            L.mom, L.n_cell, L.sg.ncell, const_cast<double*>(L.sg.cells));
@@ -1879,12 +1952,14 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         es.sample = L.sample;
         es.stride = L.sample_stride;
         es.n_sample = L.n_sample;
+        es.list = nullptr;
         hipLaunchKernelGGL(k_ewald, dim3(unsigned(L.sample_ewald_blocks)), dim3(et), lds,
                            c->stream, es);
         SurrogateArgs ss = L.sg;
         ss.sample = L.sample;
         ss.stride = L.sample_stride;
         ss.n_sample = L.n_sample;
+        ss.list = nullptr;
         hipLaunchKernelGGL(k_ewald_surrogate, dim3(unsigned(L.sample_surrogate_blocks)),
                            dim3(kSurrogateThreads), 0, c->stream, ss);
         hipLaunchKernelGGL(k_ewald_judge, dim3(1), dim3(kJudgeThreads), 0, c->stream, L.r.ctl,
@@ -1895,8 +1970,7 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
                            dim3(kSurrogateThreads), 0, c->stream, sg);
         EwaldArgs eg = L.e;
         eg.gate = L.r.ctl;
-        hipLaunchKernelGGL(k_ewald, dim3(unsigned(L.gated_ewald_blocks)), dim3(et), lds,
-                           c->stream, eg);
+        launch_ewald_all(c, L, eg);
     }
     if (phase == 2)
         hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
