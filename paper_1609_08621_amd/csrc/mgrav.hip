@@ -6,14 +6,18 @@
 // Sec. 3.3 assigns PP, PC and Ewald work to the GPU; Sec. 3.2 restricts
 // work to the active particles of a substep.
 //
-// Launch sequence of one mgrav_compute (captured in a HIP graph):
-//   k_reset        control block (queue head, counters)
-//   k_select       active buckets -> work queue, interaction counts
+// Launch sequence of one mgrav_compute (one HIP graph, or direct launches):
+//   k_select       active buckets -> cost bins, interaction counts, the
+//                  list of active particles; its last block orders the bins
+//   k_order_scatter  work queue, most expensive bins first
 //   k_interact     persistent: PP + PC for every queued sink bucket
 //   k_ewald_setup  root coefficients and k-space table (periodic only)
 //   k_ewald        FP64 Ewald correction per active particle, added to
-//                  the float tree sums in double and rounded once
-// mgrav_bind enqueues the staging kernels k_stage_* once per problem.
+//                  the float tree sums in double and rounded once (or the
+//                  learned correction, or both with the judge)
+//   k_copy_control counters to the host, then cleared for the next compute
+// The first compute after mgrav_bind starts with the staging kernels
+// k_stage_* (cell info, particles, cell records, PP entries).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -64,7 +68,26 @@ struct Control {
     int ew_fallback;                // surrogate judge: 1 = exact path taken
     int ew_pad;
     unsigned long long n_list;      // active particles listed by k_select (mask set)
+    int sel_done;                   // k_select blocks finished (the last one orders the bins)
+    int pad2;
 };
+
+// Per-compute fields back to zero: at the end of every compute (after the
+// copy to the host) and at staging, so each compute starts from zero
+// without a kernel of its own.  One block; every thread may call it.
+__device__ void reset_compute_counters(Control* ctl) {
+    if (threadIdx.x == 0) {
+        ctl->n_items = 0;
+        ctl->head = 0;
+        ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
+        ctl->ew_err = 0.0;
+        ctl->ew_samples = 0;
+        ctl->ew_fallback = 0;
+        ctl->n_list = 0;
+        ctl->sel_done = 0;
+    }
+    for (int q = threadIdx.x; q < kCostBins; q += blockDim.x) ctl->bin_count[q] = 0;
+}
 
 // Image shifts in units of L: id 0 the box, 1..26 lexicographic {-1,0,1}^3.
 __constant__ signed char c_shift[27][3] = {
@@ -166,29 +189,23 @@ struct StageArgs {
 
 // The control block (counters, error bits) into pinned host memory: the
 // last kernel of a compute; the host reads it after the completion event.
-__global__ void k_copy_control(const Control* ctl, Control* host) {
+__global__ void k_copy_control(Control* ctl, Control* host) {
     const int* src = reinterpret_cast<const int*>(ctl);
     int* dst = reinterpret_cast<int*>(host);
     for (int i = threadIdx.x; i < int(sizeof(Control) / sizeof(int)); i += blockDim.x)
         dst[i] = src[i];
-}
-
-__global__ void k_init_control(Control* ctl) {
-    if (threadIdx.x == 0) {
-        ctl->err = 0;
-        ctl->n_items = 0;
-        ctl->head = 0;
-        ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
-        ctl->ew_err = 0.0;
-        ctl->ew_samples = 0;
-        ctl->ew_fallback = 0;
-        ctl->n_list = 0;
-    }
+    __syncthreads();
+    reset_compute_counters(ctl);
 }
 
 // (0) cells: bounding-box centre and, for a valid bucket (a leaf with
 // 1..16 particles inside [0, n)), its particle range.
+// Block 0 also clears the control block (error bits and counters).
 __global__ void k_stage_cellinfo(StageArgs a) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) a.ctl->err = 0;
+        reset_compute_counters(a.ctl);
+    }
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
     const double* bb = a.bbox + 6 * c;
@@ -412,19 +429,6 @@ struct RunArgs {
     int* plist;  // with a mask: the active particles, for the Ewald kernels
 };
 
-__global__ void k_reset(Control* ctl) {
-    if (threadIdx.x == 0) {
-        ctl->n_items = 0;
-        ctl->head = 0;
-        ctl->n_pp_int = ctl->n_pc_int = ctl->n_active_p = ctl->n_active_b = 0;
-        ctl->ew_err = 0.0;
-        ctl->ew_samples = 0;
-        ctl->ew_fallback = 0;
-        ctl->n_list = 0;
-    }
-    if (threadIdx.x < kCostBins) ctl->bin_count[threadIdx.x] = 0;
-}
-
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
     for (int o = 1; o < kWave; o <<= 1) {
         const int t = __shfl_up(v, o);
@@ -512,6 +516,7 @@ __global__ void __launch_bounds__(kSelectThreads) k_select(RunArgs a) {
     __syncthreads();
     if (threadIdx.x < kCostBins && hist[threadIdx.x])
         atomicAdd(&a.ctl->bin_count[threadIdx.x], hist[threadIdx.x]);
+    __shared__ int last;
     if (threadIdx.x == 0) {
         unsigned long long s[4] = {0, 0, 0, 0};
         for (int i = 0; i < kSelectThreads / kWave; ++i)
@@ -523,18 +528,28 @@ __global__ void __launch_bounds__(kSelectThreads) k_select(RunArgs a) {
             atomicAdd(&a.ctl->n_active_b, s[3]);
         }
     }
-}
-
-// Queue order: most expensive cost bins first (longest processing time
-// first, to within a factor 2), so the persistent kernel ends on short items.
-__global__ void k_order_scan(Control* ctl) {
-    if (threadIdx.x != 0) return;
-    int off = 0;
-    for (int q = kCostBins - 1; q >= 0; --q) {
-        ctl->bin_cursor[q] = off;
-        off += ctl->bin_count[q];
+    // the last block to finish lays out the queue: most expensive cost bins
+    // first (longest processing time first, to within a factor 2), so the
+    // persistent kernel ends on short items
+    __syncthreads();  // this block's bin counts are added
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(&a.ctl->sel_done, 1) == int(gridDim.x) - 1;
     }
-    ctl->n_items = off;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x < kCostBins)  // every block's counts, read at device scope
+        hist[threadIdx.x] = __atomic_load_n(&a.ctl->bin_count[threadIdx.x], __ATOMIC_RELAXED);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int q = kCostBins - 1; q >= 0; --q) {
+            a.ctl->bin_cursor[q] = off;
+            off += hist[q];
+        }
+        a.ctl->n_items = off;
+    }
 }
 
 // Block-aggregated scatter: one global atomic per (block, bin) reserves a
@@ -1010,24 +1025,26 @@ __constant__ int c_ax4[15][4] = {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0
 constexpr int kSetupThreads = 256;
 __global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
     const double* m = a.mom;
-    const double L = a.L, L2 = L * L, L3 = L2 * L, L4 = L3 * L;
+    // unit-box scaling by multiplication (one thread runs this part: no
+    // divisions in its chain)
+    const double iL = 1.0 / a.L, iL2 = iL * iL, iL3 = iL2 * iL, iL4 = iL3 * iL;
     if (threadIdx.x == 0) {
         double r[kRec];
         r[0] = m[0];
-        r[1] = 0.5 * (m[1] + m[4] + m[6]) / L2;
-        for (int i = 0; i < 6; ++i) r[2 + i] = 0.5 * m[1 + i] / L2;
-        r[8] = -0.5 * (m[7] + m[10] + m[12]) / L3;
-        r[9] = -0.5 * (m[8] + m[13] + m[15]) / L3;
-        r[10] = -0.5 * (m[9] + m[14] + m[16]) / L3;
-        r[11] = 0.125 * (m[17] + m[27] + m[31] + 2.0 * (m[20] + m[22] + m[29])) / L4;
-        for (int i = 0; i < 10; ++i) r[12 + i] = -m[7 + i] / 6.0 / L3;
-        r[22] = 0.25 * (m[17] + m[20] + m[22]) / L4;
-        r[23] = 0.25 * (m[18] + m[23] + m[25]) / L4;
-        r[24] = 0.25 * (m[19] + m[24] + m[26]) / L4;
-        r[25] = 0.25 * (m[20] + m[27] + m[29]) / L4;
-        r[26] = 0.25 * (m[21] + m[28] + m[30]) / L4;
-        r[27] = 0.25 * (m[22] + m[29] + m[31]) / L4;
-        for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] / 24.0 / L4;
+        r[1] = 0.5 * (m[1] + m[4] + m[6]) * iL2;
+        for (int i = 0; i < 6; ++i) r[2 + i] = 0.5 * m[1 + i] * iL2;
+        r[8] = -0.5 * (m[7] + m[10] + m[12]) * iL3;
+        r[9] = -0.5 * (m[8] + m[13] + m[15]) * iL3;
+        r[10] = -0.5 * (m[9] + m[14] + m[16]) * iL3;
+        r[11] = 0.125 * (m[17] + m[27] + m[31] + 2.0 * (m[20] + m[22] + m[29])) * iL4;
+        for (int i = 0; i < 10; ++i) r[12 + i] = -m[7 + i] * (1.0 / 6.0) * iL3;
+        r[22] = 0.25 * (m[17] + m[20] + m[22]) * iL4;
+        r[23] = 0.25 * (m[18] + m[23] + m[25]) * iL4;
+        r[24] = 0.25 * (m[19] + m[24] + m[26]) * iL4;
+        r[25] = 0.25 * (m[20] + m[27] + m[29]) * iL4;
+        r[26] = 0.25 * (m[21] + m[28] + m[30]) * iL4;
+        r[27] = 0.25 * (m[22] + m[29] + m[31]) * iL4;
+        for (int i = 0; i < 15; ++i) r[28 + i] = m[17 + i] * (1.0 / 24.0) * iL4;
         r[43] = 0.0;
         if (a.order < 4) {  // drop orders 3 and 4 (and their traces)
             for (int i = 8; i < 11; ++i) r[i] = 0.0;
@@ -1077,11 +1094,11 @@ __global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
             const double h[3] = {double(hx), double(hy), double(hz)};
             double Q2 = 0, Q3 = 0, Q4 = 0;
             for (int q = 0; q < 6; ++q)
-                Q2 += c_m2[q] * m[1 + q] / L2 * h[c_ax2[q][0]] * h[c_ax2[q][1]];
+                Q2 += c_m2[q] * m[1 + q] * iL2 * h[c_ax2[q][0]] * h[c_ax2[q][1]];
             for (int q = 0; q < 10; ++q)
-                Q3 += c_m3[q] * m[7 + q] / L3 * h[c_ax3[q][0]] * h[c_ax3[q][1]] * h[c_ax3[q][2]];
+                Q3 += c_m3[q] * m[7 + q] * iL3 * h[c_ax3[q][0]] * h[c_ax3[q][1]] * h[c_ax3[q][2]];
             for (int q = 0; q < 15; ++q)
-                Q4 += c_m4[q] * m[17 + q] / L4 * h[c_ax4[q][0]] * h[c_ax4[q][1]] *
+                Q4 += c_m4[q] * m[17 + q] * iL4 * h[c_ax4[q][0]] * h[c_ax4[q][1]] *
                       h[c_ax4[q][2]] * h[c_ax4[q][3]];
             if (a.order < 4) Q3 = Q4 = 0.0;
             if (a.order < 2) Q2 = 0.0;
@@ -1892,7 +1909,6 @@ static bool phase_used(const LaunchSet& L, int phase) {
 
 // The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
 static void enqueue_stage(hipStream_t st, const StageArgs& a) {
-    hipLaunchKernelGGL(k_init_control, dim3(1), dim3(kWave), 0, st, a.ctl);
     hipLaunchKernelGGL(k_stage_cellinfo, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0,
                        st, a);
     const int64_t nt = a.n_bucket * kBucket;
@@ -1921,11 +1937,9 @@ static void launch_ewald_all(mgrav_ctx* c, const LaunchSet& L, const EwaldArgs& 
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     if (phase == 0) {
         if (L.stage) enqueue_stage(c->stream, L.s);
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
         const int64_t sel = (L.n_bucket + 255) / 256;
         hipLaunchKernelGGL(k_select, dim3(unsigned(sel < 4 * c->n_cu ? sel : 4 * c->n_cu)),
                            dim3(256), 0, c->stream, L.r);
-        hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl);
         hipLaunchKernelGGL(k_order_scatter,
                            dim3(unsigned((L.n_bucket + kScatterThreads - 1) / kScatterThreads)),
                            dim3(kScatterThreads), 0, c->stream, L.r);
