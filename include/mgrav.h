@@ -178,20 +178,26 @@ typedef struct {
     int64_t n_pc;              /* = pc_off[n_bucket] (host copy)              */
 } mgrav_problem;
 
-/* Device workspace the caller must provide to mgrav_bind for `p`. */
+/* Device workspace the caller must provide to mgrav_bind for `p`:
+ * 16 bytes per particle (staged offsets and masses) + 4 (active list),
+ * 176 + 32 bytes per cell (PC records, cell centres and ranges), 16 per
+ * PP entry, 53 per bucket (work descriptor, queue, cost bin) and about
+ * 1.6 MB of fixed tables, each segment aligned to 256 bytes. */
 mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
 
 /* Bind a problem: checks the scalar arguments on the host and arranges
- * for the staging kernels to run first in the next mgrav_compute (inside
- * its first captured graph; a mgrav_wait that comes first runs them
- * itself).  The staging kernels
+ * for the staging kernels to run first in the next mgrav_compute (a
+ * mgrav_wait that comes first runs them itself).  The staging kernels
  *   (1) store every particle as float offsets from its bucket's centre
  *       (the centre itself stays in double precision) and its mass,
  *   (2) convert each cell's moments into the float coefficients of the
  *       order-4 PC expansion,
- *   (3) turn every list entry into a float offset between the source (a
- *       bucket centre for PP, a centre of mass for PC, plus the image
- *       shift) and the sink bucket's centre, computed in double.
+ *   (3) turn every PP entry into a float offset between the source
+ *       bucket's centre plus the image shift and the sink bucket's centre,
+ *       computed in double.
+ * PC entries are read as given by the PP + PC kernel, which forms the
+ * offset of the cell's centre of mass (plus image shift) from the sink
+ * bucket's centre in double.
  * Indices in the tree and lists are checked on the device; a bad entry is
  * neutralised (never dereferenced) and reported by the next mgrav_wait as
  * BAD_TREE or BAD_LIST.  `workspace` is a device buffer of at least
@@ -282,9 +288,10 @@ mgrav_status mgrav_set_active(mgrav_ctx *ctx, const uint8_t *active_dev);
  * are computed in float with float accumulation; the Ewald correction in
  * double, added to the float sums in double and rounded once.  The self
  * pair (i, image 0) is excluded; a particle's own replicas are included.
- * Asynchronous: returns after enqueueing; use mgrav_wait.  The first call
- * after bind (or with new output pointers) captures a HIP graph of the
- * launch sequence; later calls replay it. */
+ * Asynchronous: returns after enqueueing; use mgrav_wait.  In the graph
+ * launch mode (mgrav_set_launch_mode) the first call with a given set of
+ * arguments builds a HIP graph of the launch sequence and later calls
+ * replay it; in the direct mode the kernels are enqueued one by one. */
 mgrav_status mgrav_compute(mgrav_ctx *ctx, float *acc, float *pot);
 
 /* As mgrav_compute, restricted to the parts in `parts` (MGRAV_PART_*). */

@@ -24,6 +24,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is not built; run `python -m paper_1609_08621_amd.build` "
         "(the HIP extension is required, there is no fallback)")
 
+# torch first: its HIP runtime is then the one the library binds to.  With
+# the library loaded first, the process would hold two HIP runtimes (the
+# system one and torch's), and device calls fail once torch has
+# initialised its own.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _P = ctypes.c_void_p
