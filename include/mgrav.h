@@ -179,7 +179,8 @@ typedef struct {
 } mgrav_problem;
 
 /* Device workspace the caller must provide to mgrav_bind for `p`:
- * 16 bytes per particle (staged offsets and masses) + 4 (active list),
+ * 16 bytes per particle (staged offsets and masses) + 4 (active list)
+ * + 32 (Ewald correction buffered beside the PP + PC kernel),
  * 176 + 32 bytes per cell (PC records, cell centres and ranges), 16 per
  * PP entry, 53 per bucket (work descriptor, queue, cost bin) and about
  * 1.6 MB of fixed tables, each segment aligned to 256 bytes. */
@@ -305,7 +306,9 @@ typedef struct {
     int64_t n_active_particles;
     double ms_total;             /* stream time of the last compute          */
     double ms_interact;          /* PP + PC kernel of the last compute       */
-    double ms_ewald;             /* Ewald kernels of the last compute        */
+    double ms_ewald;             /* Ewald kernels of the last compute (with  */
+                                 /* direct launches and exact Ewald they run */
+                                 /* beside the PP + PC kernel)               */
     int graph_replay;            /* 1: launched from captured HIP graphs     */
     int interact_variant;        /* PP + PC kernel variant of the last compute */
     int graph_error;             /* 0, or the HIP error code that made this  */
@@ -423,10 +426,12 @@ mgrav_status mgrav_autotune(mgrav_ctx *ctx, float *acc, float *pot, const char *
 
 /* How a compute is launched: MGRAV_LAUNCH_GRAPH (default) replays one HIP
  * graph per compute (captured at the first compute with a given set of
- * arguments); MGRAV_LAUNCH_DIRECT enqueues the kernels one by one.  Results
- * are identical; which is faster depends on the runtime (mgrav_stats
- * graph_replay tells which one the last compute used).  INVALID_ARG for
- * another value. */
+ * arguments); MGRAV_LAUNCH_DIRECT enqueues the kernels one by one, and
+ * runs the exact Ewald correction on a second stream of the context beside
+ * the PP + PC kernel (into a buffer that is added afterwards, with the same
+ * arithmetic).  Results are identical; which is faster depends on the
+ * runtime (mgrav_stats graph_replay tells which one the last compute
+ * used).  INVALID_ARG for another value. */
 enum { MGRAV_LAUNCH_GRAPH = 0, MGRAV_LAUNCH_DIRECT = 1 };
 mgrav_status mgrav_set_launch_mode(mgrav_ctx *ctx, int mode);
 

@@ -111,7 +111,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
-    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, cinfo, plist, total;
+    size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, cinfo, plist, ewbuf,
+        total;
 };
 
 // Per cell, written first by the staging: the bounding-box centre and, for
@@ -155,6 +156,8 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(CellInfo) * n_cell);
     l.plist = o;
     o += align256(sizeof(int) * n);
+    l.ewbuf = o;
+    o += align256(sizeof(double) * 4 * n);
     l.total = o;
     return l;
 }
@@ -1001,6 +1004,10 @@ struct EwaldArgs {
     // j < ctl->n_list, taken by a grid-stride loop over a bounded grid.
     const int* list;
     const Control* ctl;
+    // With `ewbuf` set (the correction overlaps the PP + PC kernel): the
+    // correction goes to ewbuf[4 i + 0..3] (acceleration, potential) in
+    // double, and k_ewald_add adds it once the PP + PC sums are written.
+    double* ewbuf;
 };
 
 // Packed symmetric components of orders 2, 3, 4: multiplicity (number of
@@ -1352,6 +1359,12 @@ __device__ __forceinline__ void ewald_particle(const EwaldArgs& a, int64_t i, do
         out[5] = a.accumulate ? double(*py) : 0.0;
         out[6] = a.accumulate ? double(*pz) : 0.0;
         out[7] = 0.0;
+    } else if (a.ewbuf) {
+        double* e = a.ewbuf + 4 * i;
+        e[0] = ax;
+        e[1] = ay;
+        e[2] = az;
+        e[3] = phi;
     } else if (a.accumulate) {
         *px = float(double(*px) + ax);
         *py = float(double(*py) + ay);
@@ -1392,6 +1405,25 @@ k_ewald_list(EwaldArgs a) {
     for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < count;
          j += int64_t(gridDim.x) * blockDim.x)
         ewald_particle(a, a.list[j], nullptr, ew_lds);
+}
+
+// The buffered correction added to the PP + PC sums, in double and rounded
+// once (the same arithmetic as the accumulating epilogue above).
+__global__ void __launch_bounds__(256) k_ewald_add(EwaldArgs a) {
+    const int64_t count = a.list ? int64_t(a.ctl->n_list) : a.n;
+    for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < count;
+         j += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = a.list ? int64_t(a.list[j]) : j;
+        if (!a.list && a.active && !a.active[i]) continue;
+        const double* e = a.ewbuf + 4 * i;
+        float* px = a.acc + i;
+        float* py = a.acc + a.n + i;
+        float* pz = a.acc + 2 * a.n + i;
+        *px = float(double(*px) + e[0]);
+        *py = float(double(*py) + e[1]);
+        *pz = float(double(*pz) + e[2]);
+        a.pot[i] = float(double(a.pot[i]) + e[3]);
+    }
 }
 
 // The surrogate's verdict from the sample (one block, fixed summation
@@ -1470,6 +1502,7 @@ mgrav_status set_host_error(mgrav_status s, const std::string& msg) {
 struct mgrav_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;  // direct launches: exact Ewald beside the PP + PC kernel
     int n_cu = 0;
     std::string arch;  // gcnArchName, part of the autotuning cache key
     int interact_blocks[kNumVariants] = {};  // persistent grid per variant
@@ -1485,6 +1518,8 @@ struct mgrav_ctx {
     const uint8_t* active = nullptr;
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_e1 = nullptr;  // around k_interact / k_ewald
+    hipEvent_t ev_e0 = nullptr;       // start of the Ewald work when it overlaps k_interact
+    bool last_overlap = false;        // the last compute ran the Ewald on the side stream
     bool have_run = false;
     // graph cache: the captured launch sequence and the arguments it holds,
     // one set for computes that start with the staging of a fresh bind and
@@ -1678,7 +1713,8 @@ mgrav_status mgrav_create(int device, void* hip_stream, mgrav_ctx** out) {
     }
     if (hipEventCreate(&c->ev_start) != hipSuccess || hipEventCreate(&c->ev_end) != hipSuccess ||
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
-        hipEventCreate(&c->ev_e1) != hipSuccess ||
+        hipEventCreate(&c->ev_e1) != hipSuccess || hipEventCreate(&c->ev_e0) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->host_ctl), sizeof(Control)) != hipSuccess) {
         mgrav_destroy(c);
         return fail(nullptr, MGRAV_ERR_DEVICE, "event / pinned allocation failed");
@@ -1691,12 +1727,15 @@ void mgrav_destroy(mgrav_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     drop_graph(c);
     if (c->ev_start) (void)hipEventDestroy(c->ev_start);
     if (c->ev_end) (void)hipEventDestroy(c->ev_end);
     if (c->ev_k0) (void)hipEventDestroy(c->ev_k0);
     if (c->ev_k1) (void)hipEventDestroy(c->ev_k1);
     if (c->ev_e1) (void)hipEventDestroy(c->ev_e1);
+    if (c->ev_e0) (void)hipEventDestroy(c->ev_e0);
+    if (c->side) (void)hipStreamDestroy(c->side);
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
     delete c;
 }
@@ -1921,16 +1960,17 @@ static void enqueue_stage(hipStream_t st, const StageArgs& a) {
 
 // Exact correction of every active particle: one thread per particle, or,
 // with a mask, a bounded grid over the list of active particles.
-static void launch_ewald_all(mgrav_ctx* c, const LaunchSet& L, const EwaldArgs& e) {
+static void launch_ewald_all(mgrav_ctx* c, const LaunchSet& L, const EwaldArgs& e,
+                             hipStream_t st) {
     const int et = ewald_threads(e.hmax);
     const size_t lds = ewald_lds_bytes(e.hmax);
     const int64_t nb = (L.n + et - 1) / et;
     if (e.list) {
         const int64_t cap = 16 * int64_t(c->n_cu);
-        hipLaunchKernelGGL(k_ewald_list, dim3(unsigned(nb < cap ? nb : cap)), dim3(et), lds,
-                           c->stream, e);
+        hipLaunchKernelGGL(k_ewald_list, dim3(unsigned(nb < cap ? nb : cap)), dim3(et), lds, st,
+                           e);
     } else {
-        hipLaunchKernelGGL(k_ewald, dim3(unsigned(nb)), dim3(et), lds, c->stream, e);
+        hipLaunchKernelGGL(k_ewald, dim3(unsigned(nb)), dim3(et), lds, st, e);
     }
 }
 
@@ -1947,7 +1987,7 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
         launch_interact(L.variant, dim3(unsigned(L.interact_blocks)), c->stream, L.r);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_EXACT) {
         hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->stream, L.e);
-        launch_ewald_all(c, L, L.e);
+        launch_ewald_all(c, L, L.e, c->stream);
     } else if (phase == 2 && L.ewald == MGRAV_EWALD_SURROGATE) {
         hipLaunchKernelGGL(k_surrogate_cells, dim3(1), dim3(kWave), 0, c->stream, L.child, L.com,
                            L.mom, L.n_cell, L.sg.ncell, const_cast<double*>(L.sg.cells));
@@ -1984,7 +2024,7 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
                            dim3(kSurrogateThreads), 0, c->stream, sg);
         EwaldArgs eg = L.e;
         eg.gate = L.r.ctl;
-        launch_ewald_all(c, L, eg);
+        launch_ewald_all(c, L, eg, c->stream);
     }
     if (phase == 2)
         hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
@@ -2089,8 +2129,36 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
         drop_set(c, L.stage);
         if (!c->direct) capture_graphs(c, L);
     }
+    bool overlap = false;
     if (g.gexec[0]) {
         HIP_TRY(c, hipGraphLaunch(g.gexec[0], c->stream));
+    } else if (L.tree && L.ewald == MGRAV_EWALD_EXACT) {
+        // the exact correction on the side stream, into a double buffer,
+        // beside the PP + PC kernel; then added to its sums on the stream
+        HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+        enqueue_phase(c, L, 0);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipEventRecord(c->ev_k0, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_k0, 0));
+        HIP_TRY(c, hipEventRecord(c->ev_e0, c->side));
+        EwaldArgs e = L.e;
+        e.ewbuf = reinterpret_cast<double*>(c->ws + c->lay.ewbuf);
+        hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->side, e);
+        launch_ewald_all(c, L, e, c->side);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipEventRecord(c->ev_e1, c->side));
+        enqueue_phase(c, L, 1);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipEventRecord(c->ev_k1, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_e1, 0));
+        const int64_t nb = (L.n + 255) / 256;
+        hipLaunchKernelGGL(k_ewald_add, dim3(unsigned(nb < 8 * c->n_cu ? nb : 8 * c->n_cu)),
+                           dim3(256), 0, c->stream, e);
+        hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
+                           L.host_ctl);
+        HIP_TRY(c, hipGetLastError());
+        HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
+        overlap = true;
     } else {
         const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
         HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
@@ -2101,6 +2169,7 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
         }
         HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
     }
+    c->last_overlap = overlap;
     // counters and error bits travel back with the work: the last kernel of
     // phase 2 copies the control block into pinned host memory
     c->have_run = true;
@@ -2166,7 +2235,8 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
                 stats->ms_total = ms;
             if (hipEventElapsedTime(&ms, c->ev_k0, c->ev_k1) == hipSuccess)
                 stats->ms_interact = ms;
-            if (hipEventElapsedTime(&ms, c->ev_k1, c->ev_e1) == hipSuccess)
+            if (hipEventElapsedTime(&ms, c->last_overlap ? c->ev_e0 : c->ev_k1, c->ev_e1) ==
+                hipSuccess)
                 stats->ms_ewald = ms;
             const mgrav_ctx::GraphSet* g = c->last_set >= 0 ? &c->gs[c->last_set] : nullptr;
             stats->graph_replay = g && g->gexec[0] != nullptr ? 1 : 0;
