@@ -203,20 +203,28 @@ def test_autotune_chooses_and_caches(mg_ctx, tmp_path):
 
 
 def test_launch_modes_give_identical_results(mg_ctx):
+    """Graph launches (phases in sequence) and direct launches (exact Ewald
+    on a second stream beside the PP + PC kernel, added afterwards) give
+    bitwise equal results, with all particles active and with a mask (the
+    Ewald kernels then walk the list of active particles)."""
     mg, ctx = mg_ctx
     ps = workloads.make(3, scale_n1d=20)
     tree, lists, pos_t, mass_t = prepared(ps)
-    _case("graph and direct launches, clustered_20, bitwise equal")
-    out = {}
-    try:
-        for mode in (mg.LAUNCH_GRAPH, mg.LAUNCH_DIRECT):
-            ctx.set_launch_mode(mode)
-            a, p_, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t)
-            assert st.graph_replay == (1 if mode == mg.LAUNCH_GRAPH else 0), st.graph_error
-            out[mode] = (a, p_)
-    finally:
-        ctx.set_launch_mode(mg.LAUNCH_GRAPH)
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    act = (np.random.default_rng(11).random(ps.n) < 0.3).astype(np.uint8)
+    for mask in (None, act):
+        _case(f"graph and direct launches, clustered_20, mask={mask is not None}, bitwise equal")
+        out = {}
+        try:
+            for mode in (mg.LAUNCH_GRAPH, mg.LAUNCH_DIRECT):
+                ctx.set_launch_mode(mode)
+                a, p_, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, active=mask)
+                assert st.graph_replay == (1 if mode == mg.LAUNCH_GRAPH else 0), st.graph_error
+                out[mode] = (a, p_)
+        finally:
+            ctx.set_launch_mode(mg.LAUNCH_GRAPH)
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+        if mask is not None:  # inactive entries untouched in both modes
+            assert np.all(out[1][0][act == 0] == 0) and np.all(out[1][1][act == 0] == 0)
 
 
 def test_lattice_periodic_full_size_sampled(mg_ctx):
