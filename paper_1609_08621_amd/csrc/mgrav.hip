@@ -17,7 +17,8 @@
 //                  learned correction, or both with the judge)
 //   k_copy_control counters to the host, then cleared for the next compute
 // The first compute after mgrav_bind starts with the staging kernels
-// k_stage_* (cell info, particles, cell records, PP entries).
+// k_stage_cells (cell records, centres, bucket ranges) and k_stage_bucket
+// (particles, PP entries, work descriptors).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -201,59 +202,6 @@ __global__ void k_copy_control(Control* ctl, Control* host) {
     reset_compute_counters(ctl);
 }
 
-// (0) cells: bounding-box centre and, for a valid bucket (a leaf with
-// 1..16 particles inside [0, n)), its particle range.
-// Block 0 also clears the control block (error bits and counters).
-__global__ void k_stage_cellinfo(StageArgs a) {
-    if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) a.ctl->err = 0;
-        reset_compute_counters(a.ctl);
-    }
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= a.n_cell) return;
-    const double* bb = a.bbox + 6 * c;
-    CellInfo ci;
-    ci.cx = 0.5 * (bb[0] + bb[3]);
-    ci.cy = 0.5 * (bb[1] + bb[4]);
-    ci.cz = 0.5 * (bb[2] + bb[5]);
-    const int64_t f = a.cell_first[c];
-    const int k = a.cell_count[c];
-    const bool ok = a.child[2 * c] < 0 && k >= 1 && k <= kBucket && f >= 0 && f + k <= a.n;
-    ci.first = ok ? int(f) : 0;
-    ci.count = ok ? k : 0;
-    a.cinfo[c] = ci;
-}
-
-// (1) particles: float offset from the bucket's bounding-box centre + mass.
-__global__ void k_stage_particles(StageArgs a) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t b = t / kBucket;
-    const int k = int(t % kBucket);
-    if (b >= a.n_bucket) return;
-    const int64_t c = a.bucket_cell[b];
-    const CellInfo ci = c >= 0 && c < a.n_cell ? a.cinfo[c] : CellInfo{0.0, 0.0, 0.0, 0, 0};
-    if (ci.count == 0) {
-        if (k == 0) {
-            atomicOr(&a.ctl->err, kErrTree);
-            a.work[b].first = 0;
-            a.work[b].nsink = 0;
-        }
-        return;
-    }
-    if (k < ci.count) {
-        const int64_t p = ci.first + k;
-        const double x = a.pos[3 * p], y = a.pos[3 * p + 1], z = a.pos[3 * p + 2];
-        const double m = a.mass[p];
-        if (!(isfinite(x) && isfinite(y) && isfinite(z) && m > 0.0 && isfinite(m)))
-            atomicOr(&a.ctl->err, kErrParticle);
-        a.pdat[p] = make_float4(float(x - ci.cx), float(y - ci.cy), float(z - ci.cz), float(m));
-    }
-    if (k == 0) {
-        a.work[b].first = ci.first;
-        a.work[b].nsink = ci.count;
-    }
-}
-
 // Inverse of the length unit in which a cell's PC interactions are
 // evaluated: 2^-e with 2^e the smallest power of two above both the
 // softening length and the distance from the centre of mass to the
@@ -281,9 +229,31 @@ __device__ float cell_inv_unit(const StageArgs& a, int64_t c) {
 // and t = 1 / unit in the last word.  (Staging moments and records through
 // LDS for contiguous access, or four lanes per cell each storing a quarter,
 // measured slower.)
+//
+// Also, per cell, the bounding-box centre and, for a valid bucket (a leaf
+// with 1..16 particles inside [0, n)), its particle range (CellInfo), and
+// block 0 clears the control block (error bits and counters): this is the
+// first staging kernel.
 __global__ void k_stage_cells(StageArgs a) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) a.ctl->err = 0;
+        reset_compute_counters(a.ctl);
+    }
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
+    {
+        const double* bb = a.bbox + 6 * c;
+        CellInfo ci;
+        ci.cx = 0.5 * (bb[0] + bb[3]);
+        ci.cy = 0.5 * (bb[1] + bb[4]);
+        ci.cz = 0.5 * (bb[2] + bb[5]);
+        const int64_t f = a.cell_first[c];
+        const int k = a.cell_count[c];
+        const bool ok = a.child[2 * c] < 0 && k >= 1 && k <= kBucket && f >= 0 && f + k <= a.n;
+        ci.first = ok ? int(f) : 0;
+        ci.count = ok ? k : 0;
+        a.cinfo[c] = ci;
+    }
     const double* m = a.mom + 32 * c;
     double r[kRec];
     r[0] = m[0];
@@ -318,65 +288,71 @@ __global__ void k_stage_cells(StageArgs a) {
                              float(r[4 * i + 3]));
 }
 
-// (3) PP entries: offset between the source bucket's centre (plus image
-// shift) and the sink bucket's centre, in double, rounded to float; the
-// source's first particle and count packed into the fourth word.  Also
-// checks the bucket's PC range; the PC entries themselves are read, checked
-// and turned into offsets by the interact kernel.  8 lanes per sink bucket
-// (8 buckets per wave), so that each wave keeps more list entries in flight.
-constexpr int kStagePPLanes = 8;
-constexpr int kStagePPRound = 4;
+// (3) per sink bucket, 16 lanes: its particles (float offsets from the
+// bucket's bounding-box centre, kept in double, and masses; lane k takes
+// particle k), its PP entries (offset between the source bucket's centre
+// plus the image shift and the sink bucket's centre, in double, rounded to
+// float; the source's first particle and count packed into the fourth
+// word; each lane keeps kStageRound entries in flight), the check of its
+// PC range, and its work descriptor.  The PC entries themselves are read,
+// checked and turned into offsets by the interact kernel.
+constexpr int kStageLanes = 16;
+constexpr int kStageRound = 4;
 __device__ inline int group_or(int v) {
-    for (int o = kStagePPLanes / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    for (int o = kStageLanes / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
     return v;
 }
 __device__ inline int group_sum(int v) {
-    for (int o = kStagePPLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    for (int o = kStageLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
-__global__ void __launch_bounds__(256) k_stage_pp(StageArgs a) {
-    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStagePPLanes;
-    const int sl = int(threadIdx.x % kStagePPLanes);
+__global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
+    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStageLanes;
+    const int sl = int(threadIdx.x % kStageLanes);
     if (b >= a.n_bucket) return;  // whole groups: the first n_bucket groups are in range
     const int64_t s = a.bucket_cell[b];
     const bool sink_ok = s >= 0 && s < a.n_cell;
+    const CellInfo ci = sink_ok ? a.cinfo[s] : CellInfo{0.0, 0.0, 0.0, 0, 0};
+    // the sink particles
+    if (ci.count == 0) {
+        if (sl == 0) atomicOr(&a.ctl->err, kErrTree);
+    } else if (sl < ci.count) {
+        const int64_t p = ci.first + sl;
+        const double x = a.pos[3 * p], y = a.pos[3 * p + 1], z = a.pos[3 * p + 2];
+        const double m = a.mass[p];
+        if (!(isfinite(x) && isfinite(y) && isfinite(z) && m > 0.0 && isfinite(m)))
+            atomicOr(&a.ctl->err, kErrParticle);
+        a.pdat[p] = make_float4(float(x - ci.cx), float(y - ci.cy), float(z - ci.cz), float(m));
+    }
+    // the PP entries
     const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
     const bool range_ok = e0 >= 0 && e0 <= e1 && e1 <= a.n_pp;
-    double C[3] = {0, 0, 0};
-    if (sink_ok) {
-        const CellInfo ci = a.cinfo[s];
-        C[0] = ci.cx;
-        C[1] = ci.cy;
-        C[2] = ci.cz;
-    }
     int nsrc = 0, self = 0, bad = 0;
     if (!range_ok || !sink_ok) bad = 1;
     if (range_ok) {
-        // kStagePPRound entries per lane per round: all their loads, then all
-        // their cell records, are in flight together
-        for (int64_t eb = e0 + sl; eb < e1; eb += kStagePPRound * kStagePPLanes) {
-            int64_t src[kStagePPRound];
-            int img[kStagePPRound];
+        for (int64_t eb = e0 + sl; eb < e1; eb += kStageRound * kStageLanes) {
+            int64_t src[kStageRound];
+            int img[kStageRound];
 #pragma unroll
-            for (int u = 0; u < kStagePPRound; ++u) {
-                const int64_t e = eb + u * kStagePPLanes;
+            for (int u = 0; u < kStageRound; ++u) {
+                const int64_t e = eb + u * kStageLanes;
                 src[u] = e < e1 ? int64_t(a.pp_src[e]) : -1;
                 img[u] = e < e1 ? int(a.pp_img[e]) : 0;
             }
-            CellInfo si[kStagePPRound];
+            CellInfo si[kStageRound];
 #pragma unroll
-            for (int u = 0; u < kStagePPRound; ++u)
+            for (int u = 0; u < kStageRound; ++u)
                 si[u] = src[u] >= 0 && src[u] < a.n_cell ? a.cinfo[src[u]]
                                                          : CellInfo{0.0, 0.0, 0.0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < kStagePPRound; ++u) {
-                const int64_t e = eb + u * kStagePPLanes;
+            for (int u = 0; u < kStageRound; ++u) {
+                const int64_t e = eb + u * kStageLanes;
                 if (e >= e1) continue;
                 float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
                 if (sink_ok && img[u] < a.n_images && si[u].count > 0) {
-                    out.x = float(si[u].cx + c_shift[img[u]][0] * a.L - C[0]);
-                    out.y = float(si[u].cy + c_shift[img[u]][1] * a.L - C[1]);
-                    out.z = float(si[u].cz + c_shift[img[u]][2] * a.L - C[2]);
+                    out.x = float(si[u].cx + c_shift[img[u]][0] * a.L - ci.cx);
+                    out.y = float(si[u].cy + c_shift[img[u]][1] * a.L - ci.cy);
+                    out.z = float(si[u].cz + c_shift[img[u]][2] * a.L - ci.cz);
                     out.w = __uint_as_float(uint32_t(si[u].first) | (uint32_t(si[u].count) << 27));
                     nsrc += si[u].count;
                     if (src[u] == s && img[u] == 0) self = 1;
@@ -395,12 +371,16 @@ __global__ void __launch_bounds__(256) k_stage_pp(StageArgs a) {
     nsrc = group_sum(nsrc);
     if (sl == 0) {
         if (bad) atomicOr(&a.ctl->err, kErrList);
-        a.work[b].self = self;
-        a.work[b].nsrc = nsrc;
-        a.work[b].pp0 = range_ok ? e0 : 0;
-        a.work[b].pp1 = range_ok ? e1 : 0;
-        a.work[b].pc0 = pc_ok && sink_ok ? g0 : 0;
-        a.work[b].pc1 = pc_ok && sink_ok ? g1 : 0;
+        BucketWork w;
+        w.first = ci.count ? ci.first : 0;
+        w.nsink = ci.count;
+        w.self = self;
+        w.nsrc = nsrc;
+        w.pp0 = range_ok ? e0 : 0;
+        w.pp1 = range_ok ? e1 : 0;
+        w.pc0 = pc_ok && sink_ok ? g0 : 0;
+        w.pc1 = pc_ok && sink_ok ? g1 : 0;
+        a.work[b] = w;
     }
 }
 
@@ -1948,14 +1928,10 @@ static bool phase_used(const LaunchSet& L, int phase) {
 
 // The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
 static void enqueue_stage(hipStream_t st, const StageArgs& a) {
-    hipLaunchKernelGGL(k_stage_cellinfo, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0,
-                       st, a);
-    const int64_t nt = a.n_bucket * kBucket;
-    hipLaunchKernelGGL(k_stage_particles, dim3(unsigned((nt + 255) / 256)), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0, st,
                        a);
-    const int64_t np = a.n_bucket * kStagePPLanes;
-    hipLaunchKernelGGL(k_stage_pp, dim3(unsigned((np + 255) / 256)), dim3(256), 0, st, a);
+    const int64_t nb = a.n_bucket * kStageLanes;
+    hipLaunchKernelGGL(k_stage_bucket, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, a);
 }
 
 // Exact correction of every active particle: one thread per particle, or,
