@@ -1374,6 +1374,18 @@ __global__ void __launch_bounds__(kEwaldThreads) k_ewald(EwaldArgs a) {
     ewald_particle(a, i, out, ew_lds);
 }
 
+// Every particle (no mask), over a grid of one wave per SIMD, for the
+// correction that runs beside the PP + PC kernel: its waves take one slot
+// per SIMD from the start, so the two kernels share every SIMD instead of
+// the correction waiting for the PP + PC kernel's tail.
+constexpr int kEwaldBesideBlocksPerCU = 2;  // 2 waves each: one per SIMD
+__global__ void __launch_bounds__(kEwaldThreads) k_ewald_beside(EwaldArgs a) {
+    extern __shared__ double2 ew_lds[];
+    for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < a.n;
+         j += int64_t(gridDim.x) * blockDim.x)
+        ewald_particle(a, j, nullptr, ew_lds);
+}
+
 // The listed active particles (a mask is in use), over a bounded grid: a
 // grid covering every particle would spend most of its time starting
 // blocks that exit, each holding its LDS tables while it does.
@@ -2111,18 +2123,37 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
     } else if (L.tree && L.ewald == MGRAV_EWALD_EXACT) {
         // the exact correction on the side stream, into a double buffer,
         // beside the PP + PC kernel; then added to its sums on the stream
+        // Without a mask and beside a 2-wave PP + PC variant, the side
+        // stream starts with the compute (the correction needs nothing from
+        // phase 0) and takes one wave per SIMD before the PP + PC kernel
+        // fills the GPU; beside a 3-wave variant (no room for that wave) or
+        // with a mask (the list of active particles comes from phase 0) it
+        // starts after phase 0 and fills the PP + PC kernel's tail.
         HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+        EwaldArgs e = L.e;
+        e.ewbuf = reinterpret_cast<double*>(c->ws + c->lay.ewbuf);
+        const bool early = !e.list && kVariantWaves[L.variant] == 2;
+        auto side_ewald = [&](hipEvent_t after) -> hipError_t {
+            hipError_t r = hipStreamWaitEvent(c->side, after, 0);
+            if (r == hipSuccess) r = hipEventRecord(c->ev_e0, c->side);
+            if (r != hipSuccess) return r;
+            hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->side, e);
+            if (early) {
+                hipLaunchKernelGGL(k_ewald_beside,
+                                   dim3(unsigned(kEwaldBesideBlocksPerCU * c->n_cu)),
+                                   dim3(ewald_threads(e.hmax)), ewald_lds_bytes(e.hmax), c->side,
+                                   e);
+            } else {
+                launch_ewald_all(c, L, e, c->side);
+            }
+            r = hipGetLastError();
+            return r == hipSuccess ? hipEventRecord(c->ev_e1, c->side) : r;
+        };
+        if (early) HIP_TRY(c, side_ewald(c->ev_start));
         enqueue_phase(c, L, 0);
         HIP_TRY(c, hipGetLastError());
         HIP_TRY(c, hipEventRecord(c->ev_k0, c->stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_k0, 0));
-        HIP_TRY(c, hipEventRecord(c->ev_e0, c->side));
-        EwaldArgs e = L.e;
-        e.ewbuf = reinterpret_cast<double*>(c->ws + c->lay.ewbuf);
-        hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->side, e);
-        launch_ewald_all(c, L, e, c->side);
-        HIP_TRY(c, hipGetLastError());
-        HIP_TRY(c, hipEventRecord(c->ev_e1, c->side));
+        if (!early) HIP_TRY(c, side_ewald(c->ev_k0));
         enqueue_phase(c, L, 1);
         HIP_TRY(c, hipGetLastError());
         HIP_TRY(c, hipEventRecord(c->ev_k1, c->stream));

@@ -211,20 +211,31 @@ def test_launch_modes_give_identical_results(mg_ctx):
     ps = workloads.make(3, scale_n1d=20)
     tree, lists, pos_t, mass_t = prepared(ps)
     act = (np.random.default_rng(11).random(ps.n) < 0.3).astype(np.uint8)
-    for mask in (None, act):
-        _case(f"graph and direct launches, clustered_20, mask={mask is not None}, bitwise equal")
-        out = {}
-        try:
-            for mode in (mg.LAUNCH_GRAPH, mg.LAUNCH_DIRECT):
-                ctx.set_launch_mode(mode)
-                a, p_, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, active=mask)
-                assert st.graph_replay == (1 if mode == mg.LAUNCH_GRAPH else 0), st.graph_error
-                out[mode] = (a, p_)
-        finally:
-            ctx.set_launch_mode(mg.LAUNCH_GRAPH)
-        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
-        if mask is not None:  # inactive entries untouched in both modes
-            assert np.all(out[1][0][act == 0] == 0) and np.all(out[1][1][act == 0] == 0)
+    info = mg.interact_variants()
+    # a 3-wave variant (correction after the queue set-up) and a 2-wave one
+    # (correction from the compute's start, one wave per SIMD)
+    variants = [next(v for v, t in enumerate(info) if t[1] == 3),
+                next(v for v, t in enumerate(info) if t[1] == 2)]
+    for variant in variants:
+        for mask in (None, act):
+            _case(f"graph and direct launches, clustered_20, variant {variant}, "
+                  f"mask={mask is not None}, bitwise equal")
+            out = {}
+            try:
+                ctx.set_interact_variant(variant)
+                for mode in (mg.LAUNCH_GRAPH, mg.LAUNCH_DIRECT):
+                    ctx.set_launch_mode(mode)
+                    a, p_, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, active=mask)
+                    assert st.graph_replay == (1 if mode == mg.LAUNCH_GRAPH else 0), \
+                        st.graph_error
+                    assert st.interact_variant == variant
+                    out[mode] = (a, p_)
+            finally:
+                ctx.set_launch_mode(mg.LAUNCH_GRAPH)
+                ctx.set_interact_variant(0)
+            assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+            if mask is not None:  # inactive entries untouched in both modes
+                assert np.all(out[1][0][act == 0] == 0) and np.all(out[1][1][act == 0] == 0)
 
 
 def test_lattice_periodic_full_size_sampled(mg_ctx):
