@@ -2237,6 +2237,8 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
             stats->n_pc_interactions = int64_t(c->host_ctl->n_pc_int);
             stats->n_active_particles = int64_t(c->host_ctl->n_active_p);
             stats->n_active_buckets = int64_t(c->host_ctl->n_active_b);
+            // a timing that cannot be read stays 0; its error is cleared so
+            // that the next launch check does not report it
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->ev_start, c->ev_end) == hipSuccess)
                 stats->ms_total = ms;
@@ -2245,6 +2247,7 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
             if (hipEventElapsedTime(&ms, c->last_overlap ? c->ev_e0 : c->ev_k1, c->ev_e1) ==
                 hipSuccess)
                 stats->ms_ewald = ms;
+            (void)hipGetLastError();
             const mgrav_ctx::GraphSet* g = c->last_set >= 0 ? &c->gs[c->last_set] : nullptr;
             stats->graph_replay = g && g->gexec[0] != nullptr ? 1 : 0;
             stats->graph_error = c->graph_error;
