@@ -685,47 +685,54 @@ __device__ __forceinline__ T load_uniform(const T* p, int64_t i) {
 // PC entry f of a list ending at f1, for a sink bucket centred at C
 // (double): the cell's record and the offset of its centre of mass (plus
 // the image shift) from C, formed in double and scaled by the cell's
-// length unit before rounding to float.  An entry with a cell index or
-// image id out of range is reported (BAD_LIST) and, like entries at or past
-// f1, gives zero moments one unit away (t = 0 makes R' = (1, 0, 0) and
-// D' = 1, so every term is finite and adds zero).
+// length unit before rounding to float.  Every lane loads a valid record,
+// so the loads need neither a branch nor a zero fill: an entry at or past
+// f1 reads the list's last entry, and an entry with a cell index or image id
+// out of range is reported (BAD_LIST) and reads cell 0.  Such lanes then get
+// t = 0 and the offset (-1, 0, 0): R' = (1, 0, 0), D' = 1 and a_0 = 0, so
+// every term is finite and adds zero.
 __device__ __forceinline__ void load_pc(const RunArgs& a, int64_t f, int64_t f1, double Cx,
                                         double Cy, double Cz, float (&r)[kRec], float& cx,
                                         float& cy, float& cz) {
-    cx = -1.f;
-    cy = 0.f;
-    cz = 0.f;
-    int cell = -1, img = 0;
-    if (f < f1) {
-        const int src = a.pc_src[f];
-        img = a.pc_img[f];
-        if (src >= 0 && src < a.n_cell && img < a.n_images)
-            cell = src;
-        else
-            atomicOr(&a.ctl->err, kErrList);
-    }
-    if (cell >= 0) {
-        const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
+    const bool in = f < f1;
+    const int64_t fc = in ? f : f1 - 1;
+    const int src = a.pc_src[fc];
+    const int im = a.pc_img[fc];
+    const bool ok = src >= 0 && src < a.n_cell && im < a.n_images;
+    if (in && !ok) atomicOr(&a.ctl->err, kErrList);
+    const bool use = in && ok;
+    const int cell = ok ? src : 0;
+    const int img = ok ? im : 0;
+    const float4* rec = reinterpret_cast<const float4*>(a.cellrec + kRec * int64_t(cell));
 #pragma unroll
-        for (int i = 0; i < kRec / 4; ++i) {
-            const float4 q = rec[i];
-            r[4 * i] = q.x;
-            r[4 * i + 1] = q.y;
-            r[4 * i + 2] = q.z;
-            r[4 * i + 3] = q.w;
-        }
-        // image id 0 is the box, 1..26 the other points of {-1,0,1}^3 in
-        // lexicographic order: k is the position in the full 27-point order
-        const int k = img == 0 ? 13 : (img <= 13 ? img - 1 : img);
-        const double t = double(r[kRec - 1]);
-        const double* X = a.com + 3 * int64_t(cell);
-        cx = float((X[0] + double(k / 9 - 1) * a.L - Cx) * t);
-        cy = float((X[1] + double(k / 3 % 3 - 1) * a.L - Cy) * t);
-        cz = float((X[2] + double(k % 3 - 1) * a.L - Cz) * t);
-    } else {
-#pragma unroll
-        for (int i = 0; i < kRec; ++i) r[i] = 0.f;
+    for (int i = 0; i < kRec / 4; ++i) {
+        const float4 q = rec[i];
+        r[4 * i] = q.x;
+        r[4 * i + 1] = q.y;
+        r[4 * i + 2] = q.z;
+        r[4 * i + 3] = q.w;
     }
+    // image id 0 is the box, 1..26 the other points of {-1,0,1}^3 in
+    // lexicographic order: k is the position in the full 27-point order
+    const int k = img == 0 ? 13 : (img <= 13 ? img - 1 : img);
+    const double t = double(r[kRec - 1]);
+    const double* X = a.com + 3 * int64_t(cell);
+    const float ox = float((X[0] + double(k / 9 - 1) * a.L - Cx) * t);
+    const float oy = float((X[1] + double(k / 3 % 3 - 1) * a.L - Cy) * t);
+    const float oz = float((X[2] + double(k % 3 - 1) * a.L - Cz) * t);
+    cx = use ? ox : -1.f;
+    cy = use ? oy : 0.f;
+    cz = use ? oz : 0.f;
+    r[kRec - 1] = use ? r[kRec - 1] : 0.f;
+}
+
+// The sink count as a value the compiler must read again where it is used:
+// the per-sink tests then stay scalar compares inside each chunk instead of
+// sixteen 64-bit lane masks hoisted out of the chunk loops, which would
+// take scalar registers that the kernel's arguments need.
+__device__ __forceinline__ int sink_count(int n) {
+    asm volatile("; sink count %0" : "+s"(n));
+    return n;
 }
 
 // Persistent PP + PC kernel.  One wavefront per work item (a sink bucket
@@ -842,9 +849,10 @@ __global__ void __launch_bounds__(kWave)
                 for (; t0 + 2 * kWave <= total; t0 += 2 * kWave) {
                     const float4 s = lds[t0 + lane];
                     const float4 s2 = lds[t0 + kWave + lane];
+                    const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < nsink) {
+                        if (i < ns) {
                             pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                             pp_one(s2.x, s2.y, s2.z, s2.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                         }
@@ -853,9 +861,10 @@ __global__ void __launch_bounds__(kWave)
                     const int t = t0 + lane;
                     // padding lanes: a massless source at the bucket centre (finite, adds 0)
                     const float4 s = t < total ? lds[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < nsink) pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                        if (i < ns) pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                 }
                 __syncthreads();
             }
@@ -876,9 +885,10 @@ __global__ void __launch_bounds__(kWave)
                         load_pc(a, c0 + kWave + lane, f1, Cx, Cy, Cz, rn, nx, ny, nz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
+                    const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < nsink) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                        if (i < ns) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
                 }
             } else {
                 for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
@@ -886,9 +896,10 @@ __global__ void __launch_bounds__(kWave)
                     load_pc(a, c0 + lane, f1, Cx, Cy, Cz, r, cx, cy, cz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
+                    const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < nsink) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                        if (i < ns) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
                 }
             }
         }
