@@ -776,14 +776,20 @@ __global__ void __launch_bounds__(kWave)
         const double Cz =
             0.5 * (load_uniform(a.bbox, 6 * sc + 2) + load_uniform(a.bbox, 6 * sc + 5));
 
-        // The bucket's sink particles are wave-uniform: read them through the
-        // constant address space so they arrive as scalar loads, all in flight
-        // together, straight into scalar registers.
+        // The bucket's sink particles are wave-uniform.  A 2-wave variant
+        // without the PC prefetch has vector registers to spare (the sinks
+        // take 48 of them, 223 in all): a vector load keeps them there and
+        // leaves the scalar registers to the kernel's arguments, which
+        // otherwise spill into vector lanes and are read back in every chunk.
+        // The other variants (168 vector registers at most with 3 waves, the
+        // prefetch's 44 more with 2) read them through the constant address
+        // space as scalar loads into scalar registers.
+        constexpr bool kSinksInVgprs = kWaves == 2 && !kPrefetch;
         float sx[kBucket], sy[kBucket], sz[kBucket];
 #pragma unroll
         for (int i = 0; i < kBucket; ++i) {
             const int p = first + (i < nsink ? i : nsink - 1);
-            const float4 q = load_uniform(a.pdat, p);
+            const float4 q = kSinksInVgprs ? a.pdat[p] : load_uniform(a.pdat, p);
             sx[i] = q.x;
             sy[i] = q.y;
             sz[i] = q.z;
