@@ -403,11 +403,15 @@ mgrav_status mgrav_mlp_train(mgrav_ctx *ctx, const double *u, const double *psi,
  *   (default 0).  INVALID_ARG out of range.
  * mgrav_autotune: on the bound problem, runs the PP + PC parts with every
  *   variant (the first run of each untimed, then at least two timed runs,
- *   more while `budget_ms` of wall time lasts), keeps the variant with the
- *   smallest median kernel time for later computes and stores it in
- *   `*chosen` (nullable).  Then it times 12 back-to-back computes of every
- *   part from a graph and from direct launches and keeps the faster launch
- *   mode (mgrav_set_launch_mode).  `acc`/`pot` (device, as for
+ *   more while `budget_ms` of wall time lasts) and ranks them by median
+ *   kernel time.  Then it times back-to-back computes of every part (3 to
+ *   12, about a quarter of `budget_ms` each) from a graph and from direct
+ *   launches, for the fastest variant and, when that one is not a 2-wave
+ *   variant, for the fastest 2-wave one too (only those leave room for the
+ *   exact Ewald correction beside the kernel), and keeps the fastest
+ *   variant and launch mode for later computes (mgrav_set_interact_variant,
+ *   mgrav_set_launch_mode); the variant is stored in `*chosen` (nullable).
+ *   `acc`/`pot` (device, as for
  *   mgrav_compute) are overwritten by the trial runs.  `ms_per_variant`
  *   (host, nullable, mgrav_interact_variants() entries) receives each
  *   median, or -1 when not timed.  `cache_path` (nullable) names a text file

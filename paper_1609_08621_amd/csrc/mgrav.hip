@@ -21,6 +21,7 @@
 // (particles, PP entries, work descriptors).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdint>
@@ -2348,6 +2349,7 @@ mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* ca
     const auto t0 = std::chrono::steady_clock::now();
     double best = 0.0;
     int best_v = saved;
+    double med_v[kNumVariants];
     for (int v = 0; v < kNumVariants; ++v) {
         c->variant = v;
         double ms[8];
@@ -2372,37 +2374,69 @@ mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* ca
             for (int j = i; j > 0 && ms[j] < ms[j - 1]; --j) std::swap(ms[j], ms[j - 1]);
         const double med = got % 2 ? ms[got / 2] : 0.5 * (ms[got / 2 - 1] + ms[got / 2]);
         if (ms_per_variant) ms_per_variant[v] = med;
+        med_v[v] = med;
         if (v == 0 || med < best) {
             best = med;
             best_v = v;
         }
     }
-    c->variant = best_v;
-    if (chosen) *chosen = best_v;
-    // launch mode: wall time of back-to-back computes of every part, from a
-    // graph and from direct launches (graphs kept unless direct is faster)
-    double per_mode[2] = {0.0, 0.0};
-    for (int mode = 0; mode < 2; ++mode) {
-        c->direct = mode == MGRAV_LAUNCH_DIRECT;
-        drop_graph(c);
-        mgrav_status st = MGRAV_OK;
-        for (int rep = 0; rep < 3 && st == MGRAV_OK; ++rep) {  // warm-up (captures)
-            st = mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
-            if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, nullptr);
-        }
-        const auto m0 = std::chrono::steady_clock::now();
-        for (int rep = 0; rep < 12 && st == MGRAV_OK; ++rep)
-            st = mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
-        if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, nullptr);
-        if (st != MGRAV_OK) {
-            c->direct = false;
-            return st;
-        }
-        per_mode[mode] =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - m0)
-                .count();
+    // Variant and launch mode together: wall time of back-to-back computes of
+    // every part, from a graph and from direct launches, for the fastest
+    // variant by its PP + PC time and, if that one is not a 2-wave variant,
+    // for the fastest 2-wave one as well: with exact Ewald and direct
+    // launches only a 2-wave variant leaves each SIMD room for the
+    // correction to run beside it from the start, which can outweigh a
+    // slower kernel.  Graphs are kept unless direct launches are faster.
+    int cand[2] = {best_v, -1};
+    if (kVariantWaves[best_v] != 2) {
+        for (int v = 0; v < kNumVariants; ++v)
+            if (kVariantWaves[v] == 2 && (cand[1] < 0 || med_v[v] < med_v[cand[1]])) cand[1] = v;
     }
-    c->direct = per_mode[1] < per_mode[0];
+    double best_wall = 0.0;
+    int final_v = best_v, final_direct = 0;
+    for (int ci = 0; ci < 2; ++ci) {
+        if (cand[ci] < 0) continue;
+        c->variant = cand[ci];
+        for (int mode = 0; mode < 2; ++mode) {
+            c->direct = mode == MGRAV_LAUNCH_DIRECT;
+            drop_graph(c);
+            // two warm-up computes (the first captures); the second, waited
+            // for, sizes the timed run: 3 to 12 computes, about a quarter
+            // of the budget
+            mgrav_status st = MGRAV_OK;
+            double one_ms = 0.0;
+            for (int rep = 0; rep < 2 && st == MGRAV_OK; ++rep) {
+                const auto w0 = std::chrono::steady_clock::now();
+                st = mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
+                if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, nullptr);
+                one_ms = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - w0).count();
+            }
+            const int reps = std::max(3, std::min(12, int(0.25 * budget_ms / (one_ms + 1e-3))));
+            const auto m0 = std::chrono::steady_clock::now();
+            for (int rep = 0; rep < reps && st == MGRAV_OK; ++rep)
+                st = mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
+            if (st == MGRAV_OK) st = mgrav_wait(c, 60.0, nullptr);
+            if (st != MGRAV_OK) {
+                c->variant = saved;
+                c->direct = false;
+                return st;
+            }
+            const double wall =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - m0)
+                    .count() / reps;
+            if ((ci == 0 && mode == 0) || wall < best_wall) {
+                best_wall = wall;
+                final_v = cand[ci];
+                final_direct = mode;
+            }
+        }
+    }
+    best_v = final_v;
+    c->variant = best_v;
+    if (c->direct != (final_direct == 1)) drop_graph(c);
+    c->direct = final_direct == 1;
+    if (chosen) *chosen = best_v;
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(c, MGRAV_ERR_INVALID_ARG, "cannot append to cache_path (variant applied)");

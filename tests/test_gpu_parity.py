@@ -186,7 +186,10 @@ def test_autotune_chooses_and_caches(mg_ctx, tmp_path):
         v, ms = ctx.autotune(acc, pot, cache_path=cache, budget_ms=500.0)
         print(f"  chose {v}, ms {['%.3f' % m for m in ms]}", flush=True)
         assert 0 <= v < len(ms) and all(m > 0 for m in ms)
-        assert v == int(np.argmin(ms))
+        # the fastest by PP + PC time, or the fastest 2-wave variant when
+        # whole computes (with the Ewald correction) favour it
+        two_wave = [i for i in range(len(ms)) if mg.interact_variants()[i][1] == 2]
+        assert v in (int(np.argmin(ms)), min(two_wave, key=lambda i: ms[i]))
         lines = open(cache).read().split("\n")
         mode = int(lines[0].split()[-1])
         assert lines[0].startswith("mgrav-autotune ") and lines[0].split()[-2] == str(v)
