@@ -635,7 +635,7 @@ __device__ __forceinline__ void pp_one(float sx, float sy, float sz, float m, fl
 // In the cell's length unit 1/t: R' = t R (the centre offset c arrives
 // scaled), eps2t = t^2 eps^2, moments of order k times t^k.  Then
 // phi = t phi'(R') and acc = t^2 acc'(R'): one factor t is folded into a_n,
-// the other into the accumulation.
+// the other into the acceleration's coefficients.
 //
 // With a_n = a0 u^n (2n-1)!!, u = -1/D, and the staged groups already
 // carrying (2n-1)!! (so the multipole_terms outputs are Q_n = (2n-1)!! P_n
@@ -662,12 +662,14 @@ __device__ __forceinline__ void pc_one(const float (&r)[kRec], float t, float cx
     const float f0 = fmaf(u, f1, r[0]);
     const float d0 = fmaf(u, d1, f1);
     A.p = fmaf(-a0, f0, A.p);
-    const float a1 = a0 * u;
+    // the second factor t rides on a1, so each acceleration component is
+    // four FMAs into its sum
+    const float a1 = (a0 * t) * u;
     const float S = a1 * fmaf(u + u, d0, f0);
     const float b2 = a1 * u, b3 = b2 * u, b4x4 = b3 * (4.f * u);  // grad Q4 = 4 v4
-    A.x = fmaf(t, S * x + b2 * g2x + b3 * g3x + b4x4 * v4x, A.x);
-    A.y = fmaf(t, S * y + b2 * g2y + b3 * g3y + b4x4 * v4y, A.y);
-    A.z = fmaf(t, S * z + b2 * g2z + b3 * g3z + b4x4 * v4z, A.z);
+    A.x = fmaf(b4x4, v4x, fmaf(b3, g3x, fmaf(b2, g2x, fmaf(S, x, A.x))));
+    A.y = fmaf(b4x4, v4y, fmaf(b3, g3y, fmaf(b2, g2y, fmaf(S, y, A.y))));
+    A.z = fmaf(b4x4, v4z, fmaf(b3, g3z, fmaf(b2, g2z, fmaf(S, z, A.z))));
 }
 
 // Load of a wave-uniform element of memory that no kernel running at the
