@@ -690,7 +690,8 @@ __device__ __forceinline__ T load_uniform(const T* p, int64_t i) {
 // the image shift) from C, formed in double and scaled by the cell's
 // length unit before rounding to float.  Every lane loads a valid record,
 // so the loads need neither a branch nor a zero fill: an entry at or past
-// f1 reads the list's last entry, and an entry with a cell index or image id
+// f1 reads the list's last entry (the caller guarantees f1 > the chunk's
+// first entry, so that entry exists), and an entry with a cell index or image id
 // out of range is reported (BAD_LIST) and reads cell 0.  Such lanes then get
 // t = 0 and the offset (-1, 0, 0): R' = (1, 0, 0), D' = 1 and a_0 = 0, so
 // every term is finite and adds zero.
@@ -883,8 +884,10 @@ __global__ void __launch_bounds__(kWave)
             if constexpr (kPrefetch) {
                 // the next chunk's records load while this one computes
                 // (44 more registers: the 2-wave variants have them)
-                float rn[kRec], nx, ny, nz;
-                load_pc(a, f0 + lane, f1, Cx, Cy, Cz, rn, nx, ny, nz);
+                // (load_pc reads entry f1 - 1 for lanes past the end, so it
+                // is called only for a non-empty list)
+                float rn[kRec], nx = 0.f, ny = 0.f, nz = 0.f;
+                if (f0 < f1) load_pc(a, f0 + lane, f1, Cx, Cy, Cz, rn, nx, ny, nz);
                 for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
                     float r[kRec];
 #pragma unroll
