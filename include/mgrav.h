@@ -305,7 +305,9 @@ typedef struct {
     int64_t n_active_buckets;
     int64_t n_active_particles;
     double ms_total;             /* stream time of the last compute          */
-    double ms_interact;          /* PP + PC kernel of the last compute       */
+    double ms_interact;          /* PP + PC kernel of the last compute: its  */
+                                 /* span on the device wall clock, from its  */
+                                 /* first queue claim to its last wave's exit */
     double ms_ewald;             /* Ewald kernels of the last compute (with  */
                                  /* direct launches and exact Ewald they run */
                                  /* beside the PP + PC kernel)               */
