@@ -115,3 +115,60 @@ def adam_step(theta, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** step)
     vh = v / (1.0 - beta2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# The learned Ewald correction applied to particles (FP64).
+#
+# The network stands for the Ewald kernel psi of Sec. 3.1 (the periodic
+# field of a unit mass minus its 27 nearest images), as a function of the
+# folded offset u = |r| / L per axis in the positive octant; its four
+# outputs are residuals of the quadratic background term:
+#   psi(u)       = y0(u) - (2 pi / 3) |u|^2 + psi(0),
+#   d psi / d u_a = y_a(u) - (4 pi / 3) u_a.
+# psi is even in every coordinate of r, so d psi / d r_a = sign(r_a) times
+# d psi / d u_a (r_a = 0 is taken with the + sign; there the exact
+# derivative is zero).  The correction at particle x from the monopoles
+# (M_c, X_c) of a set of cells is
+#   phi(x) = sum_c M_c psi((x - X_c) / L) / L,
+#   acc(x) = -sum_c M_c grad psi((x - X_c) / L) / L^2,
+# summed in double.  The network reads its input as float, so u is rounded
+# to float32 before the (double) forward pass; the weights and the two
+# inner layers' inputs are rounded to bfloat16 as on the device.
+# --------------------------------------------------------------------------
+
+def top_cells(child: np.ndarray, ncell: int) -> list:
+    """Cells at depth log2(ncell) below the root (cell 0), breadth first,
+    each parent's lower child before its upper one; a leaf reached above
+    that depth stands for its own branch.  ncell is 1, 8 or 64."""
+    depth = {1: 0, 8: 3, 64: 6}[ncell]
+    frontier = [0]
+    for _ in range(depth):
+        nxt = []
+        for c in frontier:
+            lo, hi = int(child[c][0]), int(child[c][1])
+            nxt.extend([lo, hi] if lo >= 0 else [c])
+        frontier = nxt
+    return frontier
+
+
+def surrogate_correction(theta: np.ndarray, pos: np.ndarray, cell_mass: np.ndarray,
+                         cell_com: np.ndarray, L: float, psi0: float, chunk: int = 4096):
+    """Accelerations [n,3] and potentials [n] of the learned correction at
+    positions pos [n,3] from cells (masses [k], centres of mass [k,3])."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    acc = np.zeros((n, 3))
+    pot = np.zeros(n)
+    for c in range(len(cell_mass)):
+        M = float(cell_mass[c])
+        for s in range(0, n, chunk):
+            r = (pos[s:s + chunk] - cell_com[c]) / L
+            u = np.abs(r).astype(np.float32).astype(np.float64)
+            y, _ = forward(theta, u, bf16=True)
+            psi = y[:, 0] - (2.0 * np.pi / 3.0) * np.sum(u * u, axis=1) + psi0
+            dpsi_du = y[:, 1:] - (4.0 * np.pi / 3.0) * u
+            grad = np.where(r < 0.0, -dpsi_du, dpsi_du)
+            pot[s:s + chunk] += M * psi / L
+            acc[s:s + chunk] -= M * grad / (L * L)
+    return acc, pot

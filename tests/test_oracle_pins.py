@@ -421,3 +421,122 @@ def test_periodic_tree_matches_direct_sum_within_expansion_error():
     assert _rel_rms(acc, ad[tree.perm]) < 3e-3
     momentum = (ps.mass[tree.perm, None] * acc).sum(0)
     assert np.abs(momentum).max() < 1e-3 * np.abs(acc).mean()
+
+
+# ------------------------------------------- softened PC, orders >= 2 ----
+
+@pytest.mark.parametrize("eps_over_R", [0.5, 1.0])
+def test_softened_pc_error_decays_as_fifth_power_of_cell_size(eps_over_R):
+    # Sec. 3.1 expands the softened Green's function about the cell's centre
+    # of mass.  With the softening comparable to the distance (eps = 0.5 R
+    # and eps = R), shrinking the cell at fixed R and eps must leave an
+    # order-5 remainder against the direct softened sum: the relative error
+    # falls as b^5.  If eps^2 were missing from the radial derivatives of any
+    # order >= 2, the expansion would approximate a different function and
+    # the error would stall at O(b^2) instead.
+    rng = np.random.default_rng(71)
+    base = rng.normal(size=(25, 3))
+    m = rng.uniform(0.5, 1.5, size=25)
+    R, eps = 1.0, eps_over_R * 1.0
+    direction = np.array([0.48, -0.6, 0.64])
+    # small enough that the order-6 remainder is a few per cent of the
+    # order-5 one (the potential's order-5 term is the smaller at eps = R)
+    bs = np.array([0.01, 0.014, 0.02, 0.028, 0.04])
+    ea, ep = [], []
+    for b in bs:
+        pts = b * base
+        com, mom = oracle.moments(pts, m)
+        x = com + R * direction
+        out = oracle.pc_point(mom, com, x, eps)
+        r = x - pts
+        D = (r ** 2).sum(1) + eps * eps
+        a_ex = -(m[:, None] * r / D[:, None] ** 1.5).sum(0)
+        p_ex = -(m / np.sqrt(D)).sum()
+        ea.append(np.linalg.norm(out[:3] - a_ex) / np.linalg.norm(a_ex))
+        ep.append(abs(out[3] - p_ex) / abs(p_ex))
+    sa = np.polyfit(np.log(bs), np.log(ea), 1)[0]
+    sp = np.polyfit(np.log(bs), np.log(ep), 1)[0]
+    assert 4.7 < sa < 5.3, (sa, ea)
+    assert 4.7 < sp < 5.3, (sp, ep)
+
+
+def test_softened_pc_quadrupole_closed_form():
+    # Two masses m at +-s on the x axis seen from (0, R, 0) with Plummer
+    # softening: the exact potential is -2m (R^2 + s^2 + eps^2)^(-1/2);
+    # expanded in s^2 its first two terms are -2m/S (1 - s^2/(2 S^2)),
+    # S^2 = R^2 + eps^2.  The order-4 moments reproduce the expansion
+    # through s^4: -2m/S (1 - s^2/(2S^2) + 3 s^4/(8 S^4)).
+    m, s, R, eps = 0.25, 0.05, 0.6, 0.45
+    pos = np.array([[s, 0, 0], [-s, 0, 0]])
+    com, mom = oracle.moments(pos, np.array([m, m]))
+    out = oracle.pc_point(mom, com, np.array([0.0, R, 0.0]), eps)
+    S2 = R * R + eps * eps
+    u = s * s / S2
+    expect_phi = -2 * m / math.sqrt(S2) * (1 - u / 2 + 3 * u * u / 8)
+    # d/dR of -2m (S^2 + s^2)^(-1/2) is 2m R (S^2+s^2)^(-3/2); its series
+    # through s^4 is 2m R / S^3 (1 - 3u/2 + 15 u^2/8), and acc = -grad phi
+    expect_ay = -2 * m * R / S2 ** 1.5 * (1 - 1.5 * u + 15 * u * u / 8)
+    assert np.isclose(out[3], expect_phi, rtol=1e-13)
+    assert np.isclose(out[1], expect_ay, rtol=1e-13)
+    assert abs(out[0]) < 1e-16 and abs(out[2]) < 1e-16
+
+
+# ------------------------------------------------------ box side L != 1 ----
+
+def _scaled_lattice(L):
+    ps = workloads.perturbed_lattice(4, 0.2, seed=9)
+    return ps.pos * L, ps.mass, ps.eps * L
+
+
+def test_direct_periodic_sum_scales_with_box_side():
+    # Gravity has no intrinsic length: scaling positions, softening and the
+    # box by L leaves the masses' field self-similar, with accelerations
+    # times 1/L^2 and potentials times 1/L.
+    L = 2.5
+    p1, m, e1 = _scaled_lattice(1.0)
+    pL, _, eL = _scaled_lattice(L)
+    a1, q1 = oracle.direct_periodic(p1, m, e1, 1.0)
+    aL, qL = oracle.direct_periodic(pL, m, eL, L)
+    assert np.allclose(aL * L * L, a1, rtol=1e-11, atol=1e-11 * np.abs(a1).max())
+    assert np.allclose(qL * L, q1, rtol=1e-11, atol=1e-11 * np.abs(q1).max())
+
+
+def test_tree_method_with_ewald_scales_with_box_side():
+    # The same scaling through the whole oracle path: tree, lists (the
+    # acceptance rule compares lengths only), PP, PC and the root-multipole
+    # Ewald correction with its powers of L.
+    L = 2.5
+    p1, m, e1 = _scaled_lattice(1.0)
+    pL, _, eL = _scaled_lattice(L)
+    t1 = oracle.build_tree(p1, m, 1.0, 16)
+    tL = oracle.build_tree(pL, m, L, 16)
+    assert np.array_equal(t1.perm, tL.perm) and np.array_equal(t1.child, tL.child)
+    l1 = oracle.build_lists(t1, 0.7, e1)
+    lL = oracle.build_lists(tL, 0.7, eL)
+    for f in ("pp_off", "pp_src", "pp_img", "pc_off", "pc_src", "pc_img"):
+        assert np.array_equal(getattr(l1, f), getattr(lL, f)), f
+    assert np.allclose(tL.mom[:, 1:7] / L ** 2, t1.mom[:, 1:7], rtol=1e-12, atol=1e-18)
+    a1, q1 = oracle.evaluate(t1, l1, p1[t1.perm], m[t1.perm], e1, 7)
+    aL, qL = oracle.evaluate(tL, lL, pL[tL.perm], m[tL.perm], eL, 7)
+    assert np.allclose(aL * L * L, a1, rtol=1e-10, atol=1e-10 * np.abs(a1).max())
+    assert np.allclose(qL * L, q1, rtol=1e-10, atol=1e-10 * np.abs(q1).max())
+    # the Ewald part alone, where the powers L^-(1+k) and L^-(2+k) act
+    e1a, e1q = oracle.evaluate(t1, l1, p1[t1.perm], m[t1.perm], e1, 4)
+    eLa, eLq = oracle.evaluate(tL, lL, pL[tL.perm], m[tL.perm], eL, 4)
+    assert np.allclose(eLa * L * L, e1a, rtol=1e-10, atol=1e-12 * np.abs(e1a).max())
+    assert np.allclose(eLq * L, e1q, rtol=1e-10)
+
+
+def test_ewald_root_point_scales_with_box_side():
+    # one compact source of order-4 moments, seen at the same scaled offset
+    rng = np.random.default_rng(72)
+    pts = rng.normal(size=(6, 3)) * 0.08
+    m = rng.uniform(0.5, 1.5, size=6)
+    x = np.array([0.23, -0.11, 0.37])
+    com, mom = oracle.moments(pts, m)
+    ref = oracle.ewald_root_point(mom, com, x, 1.0, 2.6, 1, 10)
+    for L in (0.4, 2.5, 7.0):
+        comL, momL = oracle.moments(pts * L, m)
+        out = oracle.ewald_root_point(momL, comL, x * L, L, 2.6, 1, 10)
+        assert np.allclose(out[:3] * L * L, ref[:3], rtol=1e-11, atol=1e-13)
+        assert np.isclose(out[3] * L, ref[3], rtol=1e-11)
