@@ -321,12 +321,23 @@ typedef struct {
     double ewald_sample_err;     /* SURROGATE_FALLBACK: err of the sample    */
 } mgrav_stats;
 
-/* Wait for the context's work with a watchdog: polls the completion event
- * until `timeout_s` (<= 0: wait forever) passes, then returns TIMEOUT and
- * marks the context failed (it must be re-bound).  Reports device-side
- * validation failures from the last bind (BAD_TREE / BAD_LIST).  stats
- * may be NULL. */
+/* Wait for the context's work with a watchdog (mgrav_watchdog_poll on an
+ * event recorded after the enqueued work): when `timeout_s` (<= 0: wait
+ * forever) passes first it returns TIMEOUT and marks the context failed (it
+ * must be re-bound); the event is released on every path.  Reports
+ * device-side validation failures from the last bind (BAD_TREE / BAD_LIST).
+ * stats may be NULL. */
 mgrav_status mgrav_wait(mgrav_ctx *ctx, double timeout_s, mgrav_stats *stats);
+
+/* The watchdog policy of mgrav_wait, on any completion query: calls
+ * query(user) until it returns 0 (done) or a negative value (failed), spinning
+ * for the first 2 ms and then sleeping 50 us (to 50 ms) or 500 us between
+ * calls; returns OK, DEVICE for a failed query, or TIMEOUT once `timeout_s`
+ * (> 0; <= 0 waits forever) has passed without completion.  The paper met
+ * GPUs that accepted work and never finished it (Appendix A); this bounds
+ * every wait.  Host only: touches no device, so it can be driven by a fake
+ * query (INVALID_ARG for a NULL query). */
+mgrav_status mgrav_watchdog_poll(int (*query)(void *user), void *user, double timeout_s);
 
 /* ------------------------------------------------------------------ */
 /* Learned Ewald correction (not in the paper; replaces the exact sums  */
@@ -432,10 +443,11 @@ mgrav_status mgrav_autotune(mgrav_ctx *ctx, float *acc, float *pot, const char *
 
 /* How a compute is launched: MGRAV_LAUNCH_GRAPH (default) replays one HIP
  * graph per compute (captured at the first compute with a given set of
- * arguments); MGRAV_LAUNCH_DIRECT enqueues the kernels one by one, and
- * runs the exact Ewald correction on a second stream of the context beside
- * the PP + PC kernel (into a buffer that is added afterwards, with the same
- * arithmetic).  Results are identical; which is faster depends on the
+ * arguments); MGRAV_LAUNCH_DIRECT enqueues the kernels one by one.  In both
+ * the exact Ewald correction runs beside the PP + PC kernel when both are
+ * computed (a parallel branch of the graph, or a second stream of the
+ * context), into a buffer that is added afterwards with the same
+ * arithmetic.  Results are identical; which is faster depends on the
  * runtime (mgrav_stats graph_replay tells which one the last compute
  * used).  INVALID_ARG for another value. */
 enum { MGRAV_LAUNCH_GRAPH = 0, MGRAV_LAUNCH_DIRECT = 1 };

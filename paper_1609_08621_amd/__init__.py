@@ -79,6 +79,10 @@ class TrainConfig(ctypes.Structure):
 MLP_PARAMS = 34052
 
 
+# int query(void *user): 0 = done, > 0 = not yet, < 0 = failed
+WATCHDOG_QUERY = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p)
+
+
 def _declare():
     L = _lib
     L.mgrav_version.restype = _I
@@ -138,6 +142,8 @@ def _declare():
     L.mgrav_autotune.argtypes = [_P, _P, _P, ctypes.c_char_p, _D, ctypes.POINTER(_I), _P]
     L.mgrav_set_launch_mode.restype = _I
     L.mgrav_set_launch_mode.argtypes = [_P, _I]
+    L.mgrav_watchdog_poll.restype = _I
+    L.mgrav_watchdog_poll.argtypes = [WATCHDOG_QUERY, _P, _D]
 
 
 _declare()
@@ -151,7 +157,7 @@ EXPORTS = (
     "mgrav_ewald_psi", "mgrav_mlp_workspace_size", "mgrav_mlp_attach", "mgrav_mlp_set_weights",
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
     "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
-    "mgrav_autotune", "mgrav_set_launch_mode",
+    "mgrav_autotune", "mgrav_set_launch_mode", "mgrav_watchdog_poll",
 )
 
 
@@ -166,6 +172,14 @@ def _check(status: int, ctx=None):
     if status != OK:
         msg = _lib.mgrav_last_error(ctx).decode(errors="replace")
         raise MgravError(status, msg)
+
+
+def watchdog_poll(query, timeout_s: float) -> int:
+    """The library's watchdog loop on a Python completion query (a callable
+    returning 0 when done, > 0 while pending, < 0 on failure); returns the
+    status code (OK, TIMEOUT or DEVICE) without raising."""
+    cb = WATCHDOG_QUERY(lambda _user: int(query()))
+    return int(_lib.mgrav_watchdog_poll(cb, None, float(timeout_s)))
 
 
 def version() -> int:

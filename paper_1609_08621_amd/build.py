@@ -18,6 +18,19 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function"]
 
 
+def source_digest() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel sources (csrc/*.hip,
+    *.inc, *.h, in name order) and the public header: identifies the build
+    in the autotuning cache."""
+    import hashlib
+    h = hashlib.sha256()
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".inc", ".h")))
+    for f in names + ["../../include/mgrav.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _run(cmd):
     print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -32,7 +45,9 @@ def build(verbose: bool = True, out: str = LIB, extra_flags=()) -> str:
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-ffp-contract=off", "-Wall",
           "-c", os.path.join(CSRC, "tree_host.cpp"), "-o", tree_o])
     dev_o = os.path.join(bdir, "mgrav.o")
-    _run(["hipcc", *HIP_FLAGS, *extra_flags, "-c", os.path.join(CSRC, "mgrav.hip"), "-o", dev_o])
+    digest = f'-DMGRAV_SOURCE_DIGEST="{source_digest()}"'
+    _run(["hipcc", *HIP_FLAGS, digest, *extra_flags, "-c", os.path.join(CSRC, "mgrav.hip"),
+          "-o", dev_o])
     tmp = out + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, dev_o, tree_o,
           "-lgomp"])

@@ -34,6 +34,12 @@
 #include "../../include/mgrav.h"
 #include "internal.h"
 
+// Digest of the kernel sources this library was built from (the build
+// script passes it; part of the autotuning cache key).
+#ifndef MGRAV_SOURCE_DIGEST
+#define MGRAV_SOURCE_DIGEST "unversioned"
+#endif
+
 namespace {
 
 constexpr int kWave = 64;
@@ -1576,6 +1582,11 @@ struct LaunchSet {
     const double* com;
     int64_t n, n_bucket, n_cell;
     int use_mask, tree, ewald, variant, interact_blocks, surrogate_blocks;
+    // exact Ewald beside the PP + PC kernel: the correction goes to the
+    // workspace's double buffer on a branch of its own (a second stream, or
+    // a parallel branch of the graph) and is added once both are done;
+    // `early`: the branch starts with the compute rather than after phase 0
+    int overlap, early;
     // SURROGATE_FALLBACK: the judge's sample
     double* sample;
     int64_t sample_stride, n_sample;
@@ -1944,6 +1955,18 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         e.accumulate = L->tree;
         e.list = plist;
         e.ctl = r.ctl;
+        if (L->tree && L->ewald == MGRAV_EWALD_EXACT) {
+            // Beside the PP + PC kernel.  Without a mask and next to a 2-wave
+            // PP + PC variant the branch starts with the compute (the
+            // correction reads only the caller's positions and root moments)
+            // and takes one wave per SIMD before the PP + PC kernel fills the
+            // GPU; next to a 3-wave variant (no room for that wave) or with a
+            // mask (the list of active particles comes from phase 0) it starts
+            // after phase 0 and fills the PP + PC kernel's tail.
+            L->overlap = 1;
+            L->early = (!e.list && kVariantWaves[L->variant] == 2) ? 1 : 0;
+            e.ewbuf = reinterpret_cast<double*>(w + c->lay.ewbuf);
+        }
     }
     if (judge) {
         // every stride-th particle, at most kMaxEwaldSamples of them
@@ -1965,14 +1988,6 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         const int64_t sb = (groups + wpb - 1) / wpb;
         L->sample_surrogate_blocks = int(sb < 8 * c->n_cu ? sb : 8 * c->n_cu);
     }
-}
-
-// The launch sequence in three phases: 0 = queue set-up, 1 = PP + PC,
-// 2 = Ewald.  Each phase is captured as its own graph so that timing
-// events can be recorded between them on the stream.
-static bool phase_used(const LaunchSet& L, int phase) {
-    // phase 2 always runs: it ends with the copy of the control block
-    return phase != 1 || L.tree;
 }
 
 // The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
@@ -1999,6 +2014,10 @@ static void launch_ewald_all(mgrav_ctx* c, const LaunchSet& L, const EwaldArgs& 
     }
 }
 
+// The launch sequence in three phases: 0 = queue set-up, 1 = PP + PC,
+// 2 = Ewald (or, with the overlap, the Ewald branch and the join).  Each
+// is captured as its own graph so that timing events can be recorded
+// between them.
 static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
     if (phase == 0) {
         if (L.stage) enqueue_stage(c->stream, L.s);
@@ -2056,15 +2075,37 @@ static void enqueue_phase(mgrav_ctx* c, const LaunchSet& L, int phase) {
                            L.host_ctl);
 }
 
+// The exact correction into the double buffer (the branch beside the
+// PP + PC kernel) and, once both are done, its addition to the PP + PC sums
+// followed by the copy of the control block (the join).
+static void enqueue_ewald_branch(mgrav_ctx* c, const LaunchSet& L, hipStream_t st) {
+    hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, st, L.e);
+    if (L.early)
+        hipLaunchKernelGGL(k_ewald_beside, dim3(unsigned(kEwaldBesideBlocksPerCU * c->n_cu)),
+                           dim3(ewald_threads(L.e.hmax)), ewald_lds_bytes(L.e.hmax), st, L.e);
+    else
+        launch_ewald_all(c, L, L.e, st);
+}
+
+static void enqueue_ewald_join(mgrav_ctx* c, const LaunchSet& L, hipStream_t st) {
+    const int64_t nb = (L.n + 255) / 256;
+    hipLaunchKernelGGL(k_ewald_add, dim3(unsigned(nb < 8 * c->n_cu ? nb : 8 * c->n_cu)),
+                       dim3(256), 0, st, L.e);
+    hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, st, L.r.ctl, L.host_ctl);
+}
+
 // One graph per compute: each phase is captured into a graph of its own,
-// and a parent graph chains them as child-graph nodes with the context's
-// timing events as event-record nodes in between (ev_start, phase 0,
-// ev_k0, phase 1, ev_k1, phase 2, ev_e1, ev_end).  The parent is built
-// explicitly because the HIP runtime PyTorch ships rejects event records
-// inside a stream capture.  On any failure the context falls back to
-// direct launches, and graph_error = 1000 * step + HIP error records why
-// (steps 1-3: capture of phase 0-2, 4: parent, 5: its nodes, 6:
-// instantiation).
+// and a parent graph holds them as child-graph nodes with the context's
+// timing events as event-record nodes in between (ev_start, phase 0, ev_k0,
+// phase 1, ev_k1, phase 2, ev_e1, ev_end).  With exact Ewald beside the
+// PP + PC kernel, the correction is a parallel branch (ev_e0, correction,
+// ev_e1) that starts after ev_start or after phase 0, and a join piece
+// (addition to the PP + PC sums, control copy) waits for both branches.
+// The parent is built explicitly because the HIP runtime PyTorch ships
+// rejects event records inside a stream capture.  On any failure the
+// context falls back to direct launches, and graph_error = 1000 * step +
+// HIP error records why (steps 1-4: capture of the pieces, 5: parent, 6:
+// its nodes, 7: instantiation).
 static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
     hipStreamCaptureStatus cs;
     if (c->no_graph) return;
@@ -2083,49 +2124,73 @@ static void capture_graphs(mgrav_ctx* c, const LaunchSet& L) {
     mgrav_ctx::GraphSet& g = c->gs[L.stage];
     int step = 0;
     hipError_t e = hipSuccess;
-    hipGraph_t phase[3] = {nullptr, nullptr, nullptr};
-    for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) {
-        if (!phase_used(L, ph)) continue;
-        step = 1 + ph;
+    // captured pieces: phase 0, 1, 2 or, with the overlap, phase 0, 1, the
+    // Ewald branch (slot 2) and the join (slot 3)
+    hipGraph_t piece[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+        if (k == 1 && !L.tree) continue;
+        if (k == 3 && !L.overlap) continue;
+        step = 1 + k;
         e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) break;
-        enqueue_phase(c, L, ph);
+        if (k < 2 || (k == 2 && !L.overlap)) enqueue_phase(c, L, k);
+        else if (k == 2) enqueue_ewald_branch(c, L, c->stream);
+        else enqueue_ewald_join(c, L, c->stream);
         const hipError_t r = hipPeekAtLastError();
-        const hipError_t ec = hipStreamEndCapture(c->stream, &phase[ph]);  // always end it
+        const hipError_t ec = hipStreamEndCapture(c->stream, &piece[k]);  // always end it
         e = r != hipSuccess ? r : ec;
     }
     hipGraph_t parent = nullptr;
     if (e == hipSuccess) {
-        step = 4;
+        step = 5;
         e = hipGraphCreate(&parent, 0);
     }
-    hipGraphNode_t prev = nullptr;
-    auto chain_event = [&](hipEvent_t ev) {
-        hipGraphNode_t n = nullptr;
-        e = hipGraphAddEventRecordNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, ev);
-        prev = n;
+    // nodes with explicit dependencies (at most two each)
+    auto add_event = [&](hipEvent_t ev, hipGraphNode_t d0, hipGraphNode_t d1) {
+        hipGraphNode_t deps[2], n = nullptr;
+        int nd = 0;
+        if (d0) deps[nd++] = d0;
+        if (d1) deps[nd++] = d1;
+        if (e == hipSuccess) e = hipGraphAddEventRecordNode(&n, parent, nd ? deps : nullptr, nd, ev);
+        return n;
     };
-    auto chain_child = [&](hipGraph_t child) {
-        hipGraphNode_t n = nullptr;
-        e = hipGraphAddChildGraphNode(&n, parent, prev ? &prev : nullptr, prev ? 1 : 0, child);
-        prev = n;
+    auto add_child = [&](hipGraph_t child, hipGraphNode_t d0, hipGraphNode_t d1) {
+        hipGraphNode_t deps[2], n = nullptr;
+        int nd = 0;
+        if (d0) deps[nd++] = d0;
+        if (d1) deps[nd++] = d1;
+        if (e == hipSuccess) e = hipGraphAddChildGraphNode(&n, parent, nd ? deps : nullptr, nd, child);
+        return n;
     };
-    if (e == hipSuccess) {
-        step = 5;
-        const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
-        chain_event(c->ev_start);
-        for (int ph = 0; ph < 3 && e == hipSuccess; ++ph) {
-            if (phase[ph]) chain_child(phase[ph]);
-            if (e == hipSuccess) chain_event(marks[ph]);
-        }
-        if (e == hipSuccess) chain_event(c->ev_end);
-    }
     if (e == hipSuccess) {
         step = 6;
+        // ev_start, phase 0, ev_k0, phase 1, ev_k1, then either phase 2,
+        // ev_e1, ev_end, or, with the overlap, the branch between ev_e0 and
+        // ev_e1 (after ev_start or after phase 0) joined with ev_k1 by the
+        // join piece, then ev_end
+        hipGraphNode_t n_start = add_event(c->ev_start, nullptr, nullptr);
+        hipGraphNode_t n_p0 = add_child(piece[0], n_start, nullptr);
+        hipGraphNode_t n_k0 = add_event(c->ev_k0, n_p0, nullptr);
+        hipGraphNode_t n_p1 = piece[1] ? add_child(piece[1], n_k0, nullptr) : n_k0;
+        hipGraphNode_t n_k1 = add_event(c->ev_k1, n_p1, nullptr);
+        hipGraphNode_t n_last = nullptr;
+        if (L.overlap) {
+            hipGraphNode_t n_e0 = add_event(c->ev_e0, L.early ? n_start : n_p0, nullptr);
+            hipGraphNode_t n_br = add_child(piece[2], n_e0, nullptr);
+            hipGraphNode_t n_e1 = add_event(c->ev_e1, n_br, nullptr);
+            n_last = add_child(piece[3], n_k1, n_e1);
+        } else {
+            hipGraphNode_t n_p2 = add_child(piece[2], n_k1, nullptr);
+            n_last = add_event(c->ev_e1, n_p2, nullptr);
+        }
+        (void)add_event(c->ev_end, n_last, nullptr);
+    }
+    if (e == hipSuccess) {
+        step = 7;
         e = hipGraphInstantiate(&g.gexec[0], parent, nullptr, nullptr, 0);
     }
-    for (hipGraph_t ph : phase)  // the parent holds copies
-        if (ph) (void)hipGraphDestroy(ph);
+    for (hipGraph_t pc : piece)  // the parent holds copies
+        if (pc) (void)hipGraphDestroy(pc);
     if (e == hipSuccess && g.gexec[0]) {
         g.graph[0] = parent;
         g.set = new LaunchSet(L);
@@ -2154,59 +2219,36 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
         drop_set(c, L.stage);
         if (!c->direct) capture_graphs(c, L);
     }
-    bool overlap = false;
     if (g.gexec[0]) {
         HIP_TRY(c, hipGraphLaunch(g.gexec[0], c->stream));
-    } else if (L.tree && L.ewald == MGRAV_EWALD_EXACT) {
-        // the exact correction on the side stream, into a double buffer,
+    } else if (L.overlap) {
+        // the exact correction on the side stream, into the double buffer,
         // beside the PP + PC kernel; then added to its sums on the stream
-        // Without a mask and beside a 2-wave PP + PC variant, the side
-        // stream starts with the compute (the correction needs nothing from
-        // phase 0) and takes one wave per SIMD before the PP + PC kernel
-        // fills the GPU; beside a 3-wave variant (no room for that wave) or
-        // with a mask (the list of active particles comes from phase 0) it
-        // starts after phase 0 and fills the PP + PC kernel's tail.
+        // (the PP + PC kernel times itself on the device clock, so no event
+        // marker sits between the phases on the stream unless the side
+        // stream needs one to start after phase 0)
         HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
-        EwaldArgs e = L.e;
-        e.ewbuf = reinterpret_cast<double*>(c->ws + c->lay.ewbuf);
-        const bool early = !e.list && kVariantWaves[L.variant] == 2;
         auto side_ewald = [&](hipEvent_t after) -> hipError_t {
             hipError_t r = hipStreamWaitEvent(c->side, after, 0);
             if (r == hipSuccess) r = hipEventRecord(c->ev_e0, c->side);
             if (r != hipSuccess) return r;
-            hipLaunchKernelGGL(k_ewald_setup, dim3(1), dim3(kSetupThreads), 0, c->side, e);
-            if (early) {
-                hipLaunchKernelGGL(k_ewald_beside,
-                                   dim3(unsigned(kEwaldBesideBlocksPerCU * c->n_cu)),
-                                   dim3(ewald_threads(e.hmax)), ewald_lds_bytes(e.hmax), c->side,
-                                   e);
-            } else {
-                launch_ewald_all(c, L, e, c->side);
-            }
+            enqueue_ewald_branch(c, L, c->side);
             r = hipGetLastError();
             return r == hipSuccess ? hipEventRecord(c->ev_e1, c->side) : r;
         };
-        // (the PP + PC kernel times itself on the device clock, so no event
-        // marker sits between the phases on the stream unless the side
-        // stream needs one to start after phase 0)
-        if (early) HIP_TRY(c, side_ewald(c->ev_start));
+        if (L.early) HIP_TRY(c, side_ewald(c->ev_start));
         enqueue_phase(c, L, 0);
         HIP_TRY(c, hipGetLastError());
-        if (!early) {
+        if (!L.early) {
             HIP_TRY(c, hipEventRecord(c->ev_k0, c->stream));
             HIP_TRY(c, side_ewald(c->ev_k0));
         }
         enqueue_phase(c, L, 1);
         HIP_TRY(c, hipGetLastError());
         HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_e1, 0));
-        const int64_t nb = (L.n + 255) / 256;
-        hipLaunchKernelGGL(k_ewald_add, dim3(unsigned(nb < 8 * c->n_cu ? nb : 8 * c->n_cu)),
-                           dim3(256), 0, c->stream, e);
-        hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, L.r.ctl,
-                           L.host_ctl);
+        enqueue_ewald_join(c, L, c->stream);
         HIP_TRY(c, hipGetLastError());
         HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
-        overlap = true;
     } else {
         const hipEvent_t marks[3] = {c->ev_k0, c->ev_k1, c->ev_e1};
         HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
@@ -2217,6 +2259,7 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
         }
         HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
     }
+    const bool overlap = L.overlap != 0;
     c->last_overlap = overlap;
     // counters and error bits travel back with the work: the last kernel of
     // phase 2 copies the control block into pinned host memory
@@ -2228,6 +2271,22 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
 
 mgrav_status mgrav_compute(mgrav_ctx* c, float* acc, float* pot) {
     return mgrav_compute_parts(c, MGRAV_PART_ALL, acc, pot);
+}
+
+mgrav_status mgrav_watchdog_poll(int (*query)(void* user), void* user, double timeout_s) {
+    if (!query) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "query is NULL");
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const int q = query(user);
+        if (q == 0) return MGRAV_OK;
+        if (q < 0) return fail(nullptr, MGRAV_ERR_DEVICE, "completion query failed");
+        const double dt =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (timeout_s > 0.0 && dt > timeout_s)
+            return fail(nullptr, MGRAV_ERR_TIMEOUT, "deadline passed before completion");
+        // spin for the first 2 ms (typical steps), then back off
+        if (dt > 2e-3) std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.05 ? 50 : 500));
+    }
 }
 
 mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
@@ -2251,24 +2310,27 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
         (void)hipEventDestroy(marker);
         return hip_fail(c, e, "hipEventRecord");
     }
-    const auto t0 = std::chrono::steady_clock::now();
-    for (;;) {
-        e = hipEventQuery(marker);
-        if (e == hipSuccess) break;
-        if (e != hipErrorNotReady) {
-            (void)hipEventDestroy(marker);
-            return hip_fail(c, e, "device work failed");
+    struct EventQuery {
+        hipEvent_t ev;
+        hipError_t err;
+        static int poll(void* user) {
+            EventQuery* q = static_cast<EventQuery*>(user);
+            const hipError_t r = hipEventQuery(q->ev);
+            if (r == hipSuccess) return 0;
+            if (r == hipErrorNotReady) return 1;
+            q->err = r;
+            return -1;
         }
-        const double dt =
-            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (timeout_s > 0.0 && dt > timeout_s) {
-            c->failed = true;
-            return fail(c, MGRAV_ERR_TIMEOUT, "device work did not finish before the deadline");
-        }
-        // spin for the first 2 ms (typical steps), then back off
-        if (dt > 2e-3) std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.05 ? 50 : 500));
-    }
+    } query{marker, hipSuccess};
+    const mgrav_status ws = mgrav_watchdog_poll(&EventQuery::poll, &query, timeout_s);
+    // released on every path: a marker still pending is freed by the
+    // runtime once the work before it completes
     (void)hipEventDestroy(marker);
+    if (ws == MGRAV_ERR_TIMEOUT) {
+        c->failed = true;
+        return fail(c, MGRAV_ERR_TIMEOUT, "device work did not finish before the deadline");
+    }
+    if (ws != MGRAV_OK) return hip_fail(c, query.err, "device work failed");
     // host_ctl was filled by the control copy at the end of the staging or
     // of the last compute
     if (stats) {
@@ -2345,20 +2407,25 @@ mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* ca
     if (!(budget_ms >= 0.0)) return fail(c, MGRAV_ERR_INVALID_ARG, "budget_ms must be >= 0");
     if (ms_per_variant)
         for (int v = 0; v < kNumVariants; ++v) ms_per_variant[v] = -1.0;
-    // cache key: device, CU count and the shape of the bound lists
-    char key[256];
-    std::snprintf(key, sizeof(key), "%s/cu%d/n%lld/b%lld/pp%lld/pc%lld/img%d",
-                  c->arch.c_str(), c->n_cu, (long long)c->prob.n, (long long)c->prob.n_bucket,
-                  (long long)c->prob.n_pp, (long long)c->prob.n_pc, c->prob.n_images);
+    // cache key: the library build (digest of its kernel sources: variant
+    // indices and register strategies change between builds), device, CU
+    // count, the shape of the bound lists, the Ewald mode (with exact Ewald
+    // direct launches or the graph's parallel branch overlap it with the
+    // PP + PC kernel) and whether a mask is set
+    char key[320];
+    std::snprintf(key, sizeof(key), "%s/%s/cu%d/n%lld/b%lld/pp%lld/pc%lld/img%d/ew%d/mask%d",
+                  MGRAV_SOURCE_DIGEST, c->arch.c_str(), c->n_cu, (long long)c->prob.n,
+                  (long long)c->prob.n_bucket, (long long)c->prob.n_pp, (long long)c->prob.n_pc,
+                  c->prob.n_images, c->ewald.mode, c->active ? 1 : 0);
     if (cache_path) {
         int hit = -1;
         if (FILE* f = std::fopen(cache_path, "r")) {
             // lines "mgrav-autotune <key> <variant> <launch mode>"; other
             // lines are ignored, the last match wins
-            char line[512], k[256];
+            char line[512], k[320];
             int v = -1, m = 0, hit_mode = 0;
             while (std::fgets(line, sizeof(line), f)) {
-                if (std::sscanf(line, "mgrav-autotune %255s %d %d", k, &v, &m) == 3 &&
+                if (std::sscanf(line, "mgrav-autotune %319s %d %d", k, &v, &m) == 3 &&
                     std::strcmp(k, key) == 0 && v >= 0 && v < kNumVariants && (m == 0 || m == 1)) {
                     hit = v;
                     hit_mode = m;

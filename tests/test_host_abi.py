@@ -158,3 +158,29 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_watchdog_times_out_on_a_query_that_never_completes():
+    """The wait policy against a fake completion query that never reports
+    done (the paper's GPU that accepts work and never finishes it, Appendix
+    A): TIMEOUT after the deadline, not before; completion after a few
+    polls returns OK; a failing query returns DEVICE at once."""
+    import time
+    polls = []
+
+    def never():
+        polls.append(1)
+        return 1
+
+    t0 = time.perf_counter()
+    st = mg.watchdog_poll(never, 0.05)
+    dt = time.perf_counter() - t0
+    assert st == mg.ERR_TIMEOUT
+    assert 0.05 <= dt < 1.0 and len(polls) > 3
+    assert "deadline" in mg._lib.mgrav_last_error(None).decode()
+
+    count = iter(range(5, -1, -1))
+    assert mg.watchdog_poll(lambda: next(count), 5.0) == mg.OK
+
+    assert mg.watchdog_poll(lambda: -1, 5.0) == mg.ERR_DEVICE
+    assert mg._lib.mgrav_watchdog_poll(mg.WATCHDOG_QUERY(), None, 1.0) == mg.ERR_INVALID_ARG
