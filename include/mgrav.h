@@ -32,7 +32,8 @@
  *   - "device" pointers are HIP device (HBM) addresses on the context's
  *     GPU, "host" pointers are ordinary CPU memory.  Memory passed in is
  *     borrowed: the library never frees it, and never allocates device
- *     memory itself (the caller provides a workspace).
+ *     memory itself (the caller provides a workspace, or binds to the
+ *     library's static one with mgrav_bind_static).
  */
 #ifndef MGRAV_H
 #define MGRAV_H
@@ -208,6 +209,26 @@ mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
  * positions (same buffers) re-stages them.  Re-binding is allowed at any
  * time after the previous work on the stream. */
 mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace, size_t bytes);
+
+/* Size of the library's static workspace (64 MiB; one copy per GPU). */
+#define MGRAV_STATIC_WORKSPACE_BYTES (64LL << 20)
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * mgrav_bind, with the library's own static workspace in place of a
+ * caller buffer -- MGRAV_STATIC_WORKSPACE_BYTES of device memory per GPU,
+ * reserved when the library is loaded and held until the process ends.
+ * The call allocates nothing (no hipMalloc, no hipFree); with
+ * MGRAV_LAUNCH_DIRECT the computes that follow only enqueue kernels (the
+ * graph launch mode builds a HIP graph at its first compute).  Problems
+ * whose mgrav_workspace_size exceeds the static size fail NO_MEMORY with
+ * the two sizes in mgrav_last_error (about 5 * 10^5 particles of the
+ * configurations here fit).  Every context bound this way on one GPU
+ * shares that GPU's workspace and finds the contents the last compute on
+ * it left: re-bind before computing if another context has computed there
+ * since, and never let computes of two such contexts overlap in time (they
+ * would overwrite each other's staged data).  Other errors as mgrav_bind. */
+mgrav_status mgrav_bind_static(mgrav_ctx *ctx, const mgrav_problem *p);
 
 /* Ewald correction of the periodic box (Sec. 3.1): a multipole expansion
  * of the root cell's field in the Ewald kernel psi, evaluated in double

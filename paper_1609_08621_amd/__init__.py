@@ -43,6 +43,7 @@ PART_PP, PART_PC, PART_EWALD, PART_ALL = 1, 2, 4, 7
 EWALD_NONE, EWALD_EXACT, EWALD_SURROGATE, EWALD_SURROGATE_FALLBACK = 0, 1, 2, 3
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
 MAX_BUCKET = 16
+STATIC_WORKSPACE_BYTES = 64 << 20  # mgrav_bind_static's workspace per GPU
 
 
 class Problem(ctypes.Structure):
@@ -105,6 +106,8 @@ def _declare():
     L.mgrav_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
     L.mgrav_bind.restype = _I
     L.mgrav_bind.argtypes = [_P, ctypes.POINTER(Problem), _P, ctypes.c_size_t]
+    L.mgrav_bind_static.restype = _I
+    L.mgrav_bind_static.argtypes = [_P, ctypes.POINTER(Problem)]
     L.mgrav_set_ewald.restype = _I
     L.mgrav_set_ewald.argtypes = [_P, ctypes.POINTER(EwaldConfig)]
     L.mgrav_set_active.restype = _I
@@ -152,7 +155,7 @@ _declare()
 EXPORTS = (
     "mgrav_version", "mgrav_status_string", "mgrav_last_error", "mgrav_create",
     "mgrav_destroy", "mgrav_tree_build_host", "mgrav_lists_count_host",
-    "mgrav_lists_fill_host", "mgrav_workspace_size", "mgrav_bind", "mgrav_set_ewald",
+    "mgrav_lists_fill_host", "mgrav_workspace_size", "mgrav_bind", "mgrav_bind_static", "mgrav_set_ewald",
     "mgrav_set_active", "mgrav_compute", "mgrav_compute_parts", "mgrav_wait",
     "mgrav_ewald_psi", "mgrav_mlp_workspace_size", "mgrav_mlp_attach", "mgrav_mlp_set_weights",
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
@@ -389,6 +392,17 @@ class Context:
         self.stream.wait_stream(torch.cuda.current_stream(torch.device("cuda", self.device)))
         _check(_lib.mgrav_bind(self._h, ctypes.byref(p), _P(workspace.data_ptr()),
                                ctypes.c_size_t(workspace.numel())), self._h)
+
+    def bind_static(self, p: Problem, tensors: dict):
+        """Bind a problem to the library's static workspace (no device
+        allocation; see mgrav_bind_static).  Keeps references to the device
+        tensors."""
+        torch = self._torch
+        self._keep = dict(tensors)
+        self.problem = p
+        self.n = int(p.n)
+        self.stream.wait_stream(torch.cuda.current_stream(torch.device("cuda", self.device)))
+        _check(_lib.mgrav_bind_static(self._h, ctypes.byref(p)), self._h)
 
     def set_ewald(self, mode: int = EWALD_EXACT, alpha: float = 2.6, real_layers: int = 1,
                   h2max: int = 10, order: int = 4, top_cells: int = 1,

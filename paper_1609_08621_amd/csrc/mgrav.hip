@@ -27,6 +27,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <utility>
@@ -39,6 +40,12 @@
 #ifndef MGRAV_SOURCE_DIGEST
 #define MGRAV_SOURCE_DIGEST "unversioned"
 #endif
+
+// Workspace of mgrav_bind_static: a fixed device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses
+// its name as an address: the device address of each GPU's copy is looked
+// up once per device (scratch_address) and passed to the kernels.
+static __device__ __align__(256) unsigned char scratch[MGRAV_STATIC_WORKSPACE_BYTES];
 
 namespace {
 
@@ -1606,6 +1613,26 @@ mgrav_status hip_fail(mgrav_ctx* c, hipError_t e, const char* what) {
     return fail(c, MGRAV_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device address of each GPU's copy of `scratch`, looked up by
+// mgrav_create with that device current, once per device.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxScratchDevices] = {};
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+
+void scratch_lookup(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+}
+
 #define HIP_TRY(ctx, expr)                                   \
     do {                                                     \
         hipError_t e_ = (expr);                              \
@@ -1736,6 +1763,7 @@ mgrav_status mgrav_create(int device, void* hip_stream, mgrav_ctx** out) {
     }
     c->n_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+    scratch_lookup(device);  // the device is current
     if (hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, device) !=
         hipSuccess) {
         (void)hipGetLastError();  // tolerated: kernel spans then come from events
@@ -1816,6 +1844,33 @@ mgrav_status mgrav_bind(mgrav_ctx* c, const mgrav_problem* p, void* workspace, s
     c->stage_pending = true;
     c->bound = true;
     return MGRAV_OK;
+}
+
+mgrav_status mgrav_bind_static(mgrav_ctx* c, const mgrav_problem* p) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    mgrav_status s = check_problem(c, p);
+    if (s != MGRAV_OK) return s;
+    const size_t need = make_layout(p->n, p->n_cell, p->n_bucket, p->n_pp, p->n_pc).total;
+    if (need > size_t(MGRAV_STATIC_WORKSPACE_BYTES))
+        return fail(c, MGRAV_ERR_NO_MEMORY,
+                    "problem needs " + std::to_string(need) +
+                        " bytes of workspace; the static scratch holds " +
+                        std::to_string(size_t(MGRAV_STATIC_WORKSPACE_BYTES)) +
+                        " (bind it with mgrav_bind and a workspace)");
+    if (c->device >= kMaxScratchDevices)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "static scratch serves devices 0..63 only");
+    void* ptr = nullptr;
+    hipError_t e = hipSuccess;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ptr = g_scratch_ptr[c->device];
+        e = g_scratch_err[c->device];
+    }
+    if (!ptr)
+        return hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                        "hipGetSymbolAddress(scratch)");
+    return mgrav_bind(c, p, ptr, size_t(MGRAV_STATIC_WORKSPACE_BYTES));
 }
 
 mgrav_status mgrav_set_ewald(mgrav_ctx* c, const mgrav_ewald* cfg) {
