@@ -69,6 +69,13 @@ def _declare(L):
     L.orc_tree_build.restype = _I64
     L.orc_tree_build.argtypes = [_I64, _P, _P, _D, _I, _I64, _P, _P, _P, _P, _P, _P, _P,
                                  _P, _P, _P]
+    L.orc_tree_build_box.restype = _I64
+    L.orc_tree_build_box.argtypes = [_I64, _P, _P, _D, _I, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                     _P, _P, _P, _P]
+    L.orc_lists_count_roots.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _I, _P, _P,
+                                        _P]
+    L.orc_lists_fill_roots.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _I, _P, _P,
+                                       _P, _P, _P, _P, _P]
     L.orc_lists_count.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P]
     L.orc_lists_fill.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P, _P,
                                  _P, _P, _P]
@@ -109,6 +116,7 @@ class Tree:
     bucket_cell: np.ndarray
     box_L: float
     bucket: int
+    roots: tuple = (0,)  # checklist seeds: (0,) for one tree, two for a forest
 
     @property
     def n_cell(self) -> int:
@@ -143,9 +151,14 @@ def image_shift(img: int, L: float) -> np.ndarray:
     return out
 
 
-def build_tree(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16) -> Tree:
+def build_tree(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16,
+               root_box: Optional[np.ndarray] = None) -> Tree:
+    """Tree of Sec. 3.1 over the particles; ``root_box`` (lo xyz, hi xyz)
+    replaces the default root ([0, L)^3, or the tight bounding box when
+    open)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
+    rb = None if root_box is None else np.ascontiguousarray(root_box, dtype=np.float64)
     n = pos.shape[0]
     # room for n/2 cells first (trees of buckets hold about 2n/bucket), the
     # 2n bound only if the builder reports that n/2 is not enough
@@ -160,9 +173,9 @@ def build_tree(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16
         mom = np.empty(32 * cap)
         bc = np.empty(cap, np.int32)
         nb = np.zeros(1, np.int64)
-        nc = lib().orc_tree_build(n, _p(pos), _p(mass), float(box_L), int(bucket), cap,
-                                  _p(perm), _p(cf), _p(cc), _p(ch), _p(com), _p(bmax),
-                                  _p(bbox), _p(mom), _p(bc), _p(nb))
+        nc = lib().orc_tree_build_box(n, _p(pos), _p(mass), float(box_L), int(bucket), _p(rb),
+                                      cap, _p(perm), _p(cf), _p(cc), _p(ch), _p(com), _p(bmax),
+                                      _p(bbox), _p(mom), _p(bc), _p(nb))
         if nc >= 0:
             break
     if nc < 0:
@@ -173,22 +186,60 @@ def build_tree(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16
                 float(box_L), int(bucket))
 
 
-def build_lists(tree: Tree, theta: float, eps: float, n_images: Optional[int] = None) -> Lists:
+def build_forest(pos: np.ndarray, mass: np.ndarray, box_L: float, group: np.ndarray,
+                 bucket: int = 16) -> Tree:
+    """The two trees of Sec. 3.2: the fixed tree of the particles with
+    group 0 and the very active tree of those with group 1, built over the
+    same root box (that of all particles), stored as one forest: tree-order
+    particles of the fixed tree first, then those of the very active tree;
+    cells of the fixed tree first (root 0), then those of the very active
+    tree (root n_cell of the fixed tree).  Both groups must be non-empty."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    group = np.asarray(group) != 0
+    if box_L > 0:
+        box = np.array([0.0, 0.0, 0.0, box_L, box_L, box_L])
+    else:
+        box = np.concatenate([pos.min(0), pos.max(0)])
+    ids = [np.flatnonzero(~group), np.flatnonzero(group)]
+    trees = [build_tree(pos[i], mass[i], box_L, bucket, box) for i in ids]
+    t0, t1 = trees
+    nc0, np0 = t0.n_cell, ids[0].size
+    ch1 = t1.child.copy()
+    ch1[ch1 >= 0] += nc0
+    return Tree(np.concatenate([ids[0][t0.perm], ids[1][t1.perm]]),
+                np.concatenate([t0.cell_first, t1.cell_first + np0]),
+                np.concatenate([t0.cell_count, t1.cell_count]),
+                np.concatenate([t0.child, ch1]), np.concatenate([t0.com, t1.com]),
+                np.concatenate([t0.bmax, t1.bmax]), np.concatenate([t0.bbox, t1.bbox]),
+                np.concatenate([t0.mom, t1.mom]),
+                np.concatenate([t0.bucket_cell, t1.bucket_cell + nc0]).astype(np.int32),
+                float(box_L), int(bucket), (0, nc0))
+
+
+def build_lists(tree: Tree, theta: float, eps: float, n_images: Optional[int] = None,
+                sinks: Optional[np.ndarray] = None) -> Lists:
+    """Checklist walk of Sec. 3.1 for every bucket of the tree (or for the
+    buckets with indices ``sinks``, whose lists then come in that order),
+    seeded with the tree's roots."""
     L = tree.box_L
     if n_images is None:
         n_images = 27 if L > 0 else 1
-    nb = tree.n_bucket
+    bc = tree.bucket_cell if sinks is None else \
+        np.ascontiguousarray(tree.bucket_cell[np.asarray(sinks)], dtype=np.int32)
+    nb = bc.shape[0]
+    roots = np.ascontiguousarray(tree.roots, dtype=np.int32)
     pp_off = np.zeros(nb + 1, np.int64)
     pc_off = np.zeros(nb + 1, np.int64)
-    args = (nb, _p(tree.bucket_cell), _p(tree.child), _p(tree.com), _p(tree.bmax),
-            _p(tree.bbox), float(theta), float(eps), float(L), int(n_images))
-    lib().orc_lists_count(*args, _p(pp_off), _p(pc_off))
+    args = (nb, _p(bc), _p(tree.child), _p(tree.com), _p(tree.bmax),
+            _p(tree.bbox), float(theta), float(eps), float(L), int(n_images), roots.size,
+            _p(roots))
+    lib().orc_lists_count_roots(*args, _p(pp_off), _p(pc_off))
     pp_src = np.empty(int(pp_off[-1]), np.int32)
     pp_img = np.empty(int(pp_off[-1]), np.uint8)
     pc_src = np.empty(int(pc_off[-1]), np.int32)
     pc_img = np.empty(int(pc_off[-1]), np.uint8)
-    lib().orc_lists_fill(*args, _p(pp_off), _p(pc_off), _p(pp_src), _p(pp_img), _p(pc_src),
-                         _p(pc_img))
+    lib().orc_lists_fill_roots(*args, _p(pp_off), _p(pc_off), _p(pp_src), _p(pp_img),
+                               _p(pc_src), _p(pc_img))
     return Lists(pp_off, pp_src, pp_img, pc_off, pc_src, pc_img, int(n_images))
 
 

@@ -398,10 +398,30 @@ static void cell_properties(int64_t c, const double *pos, const double *mass, co
 
 /* Build the tree.  pos: input order, AoS [n][3].  Returns the number of
  * cells, or -1 if `cap` cells are not enough (2n always suffices). */
+/* Build the tree with the root's geometric box given (root_box: lo xyz,
+ * hi xyz), or the default root (root_box NULL).  Sec. 3.2 builds the tree
+ * of the very active particles over the geometric structure of the fixed
+ * tree: with the same root box both trees bisect space along the same
+ * planes, so their cells coincide wherever both are refined. */
+int64_t orc_tree_build_box(int64_t n, const double *pos, const double *mass, double L,
+                           int bucket, const double *root_box, int64_t cap, int64_t *perm,
+                           int64_t *cell_first, int32_t *cell_count, int32_t *child, double *com,
+                           double *bmax, double *bbox, double *mom, int32_t *bucket_cell,
+                           int64_t *n_bucket);
+
 int64_t orc_tree_build(int64_t n, const double *pos, const double *mass, double L, int bucket,
                        int64_t cap, int64_t *perm, int64_t *cell_first, int32_t *cell_count,
                        int32_t *child, double *com, double *bmax, double *bbox, double *mom,
                        int32_t *bucket_cell, int64_t *n_bucket) {
+    return orc_tree_build_box(n, pos, mass, L, bucket, NULL, cap, perm, cell_first, cell_count,
+                              child, com, bmax, bbox, mom, bucket_cell, n_bucket);
+}
+
+int64_t orc_tree_build_box(int64_t n, const double *pos, const double *mass, double L,
+                           int bucket, const double *root_box, int64_t cap, int64_t *perm,
+                           int64_t *cell_first, int32_t *cell_count, int32_t *child, double *com,
+                           double *bmax, double *bbox, double *mom, int32_t *bucket_cell,
+                           int64_t *n_bucket) {
     orc_init();
     if (n <= 0 || bucket < 1) return -1;
     TreeBuild t;
@@ -417,7 +437,12 @@ int64_t orc_tree_build(int64_t n, const double *pos, const double *mass, double 
     t.child = child;
     for (int64_t i = 0; i < n; ++i) perm[i] = i;
     double lo[3], hi[3];
-    if (L > 0.0) { /* periodic: the root is the box [0, L)^3 */
+    if (root_box) { /* the root's box is given */
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = root_box[d];
+            hi[d] = root_box[3 + d];
+        }
+    } else if (L > 0.0) { /* periodic: the root is the box [0, L)^3 */
         for (int d = 0; d < 3; ++d) {
             lo[d] = 0.0;
             hi[d] = L;
@@ -482,18 +507,23 @@ static int accept_pc(int64_t c, int img, int64_t s, const double *com, const dou
 }
 
 /* Walk one sink bucket.  If the output arrays are NULL only counts. */
+/* The checklist starts with every root (in the given order), each seen
+ * through images 0 .. n_img-1.  One root (cell 0) for a single tree; two
+ * for the fixed and the very active tree of Sec. 3.2, walked together. */
 static void walk_bucket(int64_t s, const int32_t *child, const double *com, const double *bmax,
                         const double *bbox, double theta, double eps, double L, int n_img,
-                        int64_t *npp, int64_t *npc, int32_t *pp_src, uint8_t *pp_img,
-                        int32_t *pc_src, uint8_t *pc_img) {
+                        int n_roots, const int32_t *roots, int64_t *npp, int64_t *npc,
+                        int32_t *pp_src, uint8_t *pp_img, int32_t *pc_src, uint8_t *pc_img) {
     int64_t cap = 1024, head = 0, tail = 0;
+    while (cap < 2 * (int64_t)n_roots * n_img) cap *= 2;
     int64_t *qc = (int64_t *)malloc(sizeof(int64_t) * cap);
     int *qi = (int *)malloc(sizeof(int) * cap);
-    for (int i = 0; i < n_img; ++i) {
-        qc[tail] = 0;
-        qi[tail] = i;
-        ++tail;
-    }
+    for (int r = 0; r < n_roots; ++r)
+        for (int i = 0; i < n_img; ++i) {
+            qc[tail] = roots[r];
+            qi[tail] = i;
+            ++tail;
+        }
     int64_t kpp = 0, kpc = 0;
     while (head < tail) {
         int64_t c = qc[head];
@@ -531,17 +561,19 @@ static void walk_bucket(int64_t s, const int32_t *child, const double *com, cons
     *npc = kpc;
 }
 
-/* Pass 1: per-bucket list lengths as CSR offsets (pp_off, pc_off: n_bucket+1). */
-void orc_lists_count(int64_t n_bucket, const int32_t *bucket_cell, const int32_t *child,
-                     const double *com, const double *bmax, const double *bbox, double theta,
-                     double eps, double L, int n_img, int64_t *pp_off, int64_t *pc_off) {
+/* Pass 1: per-bucket list lengths as CSR offsets (pp_off, pc_off:
+ * n_bucket+1), for a checklist seeded with the n_roots cells `roots`. */
+void orc_lists_count_roots(int64_t n_bucket, const int32_t *bucket_cell, const int32_t *child,
+                           const double *com, const double *bmax, const double *bbox,
+                           double theta, double eps, double L, int n_img, int n_roots,
+                           const int32_t *roots, int64_t *pp_off, int64_t *pc_off) {
     pp_off[0] = 0;
     pc_off[0] = 0;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t b = 0; b < n_bucket; ++b) {
         int64_t a, c;
-        walk_bucket(bucket_cell[b], child, com, bmax, bbox, theta, eps, L, n_img, &a, &c, NULL,
-                    NULL, NULL, NULL);
+        walk_bucket(bucket_cell[b], child, com, bmax, bbox, theta, eps, L, n_img, n_roots, roots,
+                    &a, &c, NULL, NULL, NULL, NULL);
         pp_off[b + 1] = a;
         pc_off[b + 1] = c;
     }
@@ -552,17 +584,36 @@ void orc_lists_count(int64_t n_bucket, const int32_t *bucket_cell, const int32_t
 }
 
 /* Pass 2: fill the lists in checklist order. */
+void orc_lists_fill_roots(int64_t n_bucket, const int32_t *bucket_cell, const int32_t *child,
+                          const double *com, const double *bmax, const double *bbox, double theta,
+                          double eps, double L, int n_img, int n_roots, const int32_t *roots,
+                          const int64_t *pp_off, const int64_t *pc_off, int32_t *pp_src,
+                          uint8_t *pp_img, int32_t *pc_src, uint8_t *pc_img) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < n_bucket; ++b) {
+        int64_t a, c;
+        walk_bucket(bucket_cell[b], child, com, bmax, bbox, theta, eps, L, n_img, n_roots, roots,
+                    &a, &c, pp_src + pp_off[b], pp_img + pp_off[b], pc_src + pc_off[b],
+                    pc_img + pc_off[b]);
+    }
+}
+
+/* The single tree: the checklist starts with its root, cell 0. */
+static const int32_t ORC_ROOT0[1] = {0};
+
+void orc_lists_count(int64_t n_bucket, const int32_t *bucket_cell, const int32_t *child,
+                     const double *com, const double *bmax, const double *bbox, double theta,
+                     double eps, double L, int n_img, int64_t *pp_off, int64_t *pc_off) {
+    orc_lists_count_roots(n_bucket, bucket_cell, child, com, bmax, bbox, theta, eps, L, n_img, 1,
+                          ORC_ROOT0, pp_off, pc_off);
+}
+
 void orc_lists_fill(int64_t n_bucket, const int32_t *bucket_cell, const int32_t *child,
                     const double *com, const double *bmax, const double *bbox, double theta,
                     double eps, double L, int n_img, const int64_t *pp_off, const int64_t *pc_off,
                     int32_t *pp_src, uint8_t *pp_img, int32_t *pc_src, uint8_t *pc_img) {
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t b = 0; b < n_bucket; ++b) {
-        int64_t a, c;
-        walk_bucket(bucket_cell[b], child, com, bmax, bbox, theta, eps, L, n_img, &a, &c,
-                    pp_src + pp_off[b], pp_img + pp_off[b], pc_src + pc_off[b],
-                    pc_img + pc_off[b]);
-    }
+    orc_lists_fill_roots(n_bucket, bucket_cell, child, com, bmax, bbox, theta, eps, L, n_img, 1,
+                         ORC_ROOT0, pp_off, pc_off, pp_src, pp_img, pc_src, pc_img);
 }
 
 /* ------------------------------------------------------------------ */
