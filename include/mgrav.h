@@ -146,6 +146,103 @@ mgrav_status mgrav_lists_fill_host(int64_t n_bucket, const int32_t *bucket_cell,
                                    uint8_t *pc_img);
 
 /* ------------------------------------------------------------------ */
+/* Device-side input preparation: the same tree and checklist walk on  */
+/* the GPU (device pointers), and the two trees of Sec. 3.2.           */
+/* ------------------------------------------------------------------ */
+
+/* Outputs of mgrav_tree_build, device memory owned by the caller, with
+ * room for `cap` cells: the arrays of mgrav_tree_build_host (perm as
+ * int64), plus the particles in tree order (pos [n][3], mass [n]), which
+ * mgrav_bind takes as they are. */
+typedef struct {
+    int64_t *perm;
+    double *pos;
+    double *mass;
+    int64_t *cell_first;
+    int32_t *cell_count;
+    int32_t *child;
+    double *com;
+    double *bmax;
+    double *bbox;
+    double *mom;
+    int32_t *bucket_cell;
+} mgrav_tree_dev;
+
+/* Device workspace of mgrav_tree_build for n particles, leaves of at most
+ * `bucket` and room for `cap` cells (about 100 bytes per particle plus
+ * 80 per cell).  INVALID_ARG for n outside 1 .. MGRAV_MAX_PARTICLES,
+ * bucket outside 1 .. MGRAV_MAX_BUCKET, cap outside 1 .. 2n + 2. */
+mgrav_status mgrav_tree_workspace_size(int64_t n, int bucket, int64_t cap, size_t *bytes);
+
+/* The tree of mgrav_tree_build_host, built on the device from pos [n][3]
+ * and mass [n] (device, input order): the same cells in the same
+ * node-left-right order, particles in the same tree order, identical
+ * bounding boxes, and for buckets identical centres of mass, b_max and
+ * moments.  A parent's mass, first moments and box come from its
+ * children (its centre of mass may differ from the host builder's
+ * particle-order sum in the last bits), its order-2..4 moments are its
+ * children's shifted to its centre of mass (the parallel-axis expansion,
+ * exact up to rounding), and its b_max is taken over its particles.
+ * With `group` (device [n] uint8, nullable) particles with group 0 and
+ * group != 0 get a tree each -- the fixed and the very active tree of
+ * Sec. 3.2 -- over the same root box (that of all particles), so that
+ * both bisect space along the same planes; they are stored as one
+ * forest: the first tree's particles (in tree order), then the second's;
+ * the first tree's cells (root 0), then the second's (root
+ * *n_cell_first), buckets likewise.  Both groups must be non-empty.
+ * Blocking (the host reads one count per level).  *n_cell_first (nullable)
+ * receives the first tree's cell count (= n_cell for one tree).  Errors:
+ * INVALID_ARG for bad sizes, non-finite input, non-positive mass, a
+ * periodic coordinate outside [0, L), an empty group, or "capacity" in
+ * the message when the tree needs more than cap cells (build again with
+ * a larger cap); NO_MEMORY for a workspace below
+ * mgrav_tree_workspace_size. */
+mgrav_status mgrav_tree_build(mgrav_ctx *ctx, int64_t n, const double *pos, const double *mass,
+                              const uint8_t *group, double L, int bucket, void *workspace,
+                              size_t bytes, int64_t cap, const mgrav_tree_dev *out,
+                              int64_t *n_cell, int64_t *n_bucket, int64_t *n_cell_first);
+
+/* The checklist walk of mgrav_lists_count_host / _fill_host on the
+ * device, for the sink buckets sink_cell[n_sink] (cells, device memory;
+ * for one tree its bucket_cell, for a forest the second tree's buckets),
+ * the checklist seeded with every root (roots[0 .. n_roots-1], host
+ * values, in that order) seen through images 0 .. n_images-1.  Tree
+ * arrays (child, com, bmax, bbox; device) as mgrav_tree_build writes
+ * them. */
+typedef struct {
+    int64_t n_cell;
+    const int32_t *child;
+    const double *com;
+    const double *bmax;
+    const double *bbox;
+    int n_roots;          /* 1 or 2 */
+    int32_t roots[2];
+    double theta, eps, L; /* theta > 0, eps >= 0, L = 0 (open) or the box */
+    int n_images;         /* 1 or 27 (L > 0) */
+    int64_t n_sink;
+    const int32_t *sink_cell;
+} mgrav_walk;
+
+/* Device workspace of the walk (96 bytes per cell, 16 per sink). */
+mgrav_status mgrav_lists_workspace_size(int64_t n_cell, int64_t n_sink, size_t *bytes);
+
+/* Pass 1: pp_off[n_sink + 1] and pc_off[n_sink + 1] (device) receive the
+ * CSR offsets of the lists; *n_pp and *n_pc (host, nullable) their
+ * totals.  Pass 2 fills pp_src, pp_img, pc_src, pc_img (device) in
+ * checklist order, with the offsets of pass 1 and the same workspace
+ * contents or a new one.  Each sink's checklist runs in a ring of 1024
+ * entries (NO_MEMORY if one outgrows it; far more than the tens of
+ * entries a checklist holds here).  BAD_TREE for a cell index outside the
+ * tree, INVALID_ARG for bad scalars.  Blocking. */
+mgrav_status mgrav_lists_count(mgrav_ctx *ctx, const mgrav_walk *walk, void *workspace,
+                               size_t bytes, int64_t *pp_off, int64_t *pc_off, int64_t *n_pp,
+                               int64_t *n_pc);
+mgrav_status mgrav_lists_fill(mgrav_ctx *ctx, const mgrav_walk *walk, void *workspace,
+                              size_t bytes, const int64_t *pp_off, const int64_t *pc_off,
+                              int32_t *pp_src, uint8_t *pp_img, int32_t *pc_src,
+                              uint8_t *pc_img);
+
+/* ------------------------------------------------------------------ */
 /* Device-side evaluation.                                             */
 /* ------------------------------------------------------------------ */
 

@@ -70,6 +70,18 @@ class Stats(ctypes.Structure):
                 ("ewald_fallback", _I), ("ewald_samples", _I64), ("ewald_sample_err", _D)]
 
 
+class TreeDev(ctypes.Structure):
+    _fields_ = [("perm", _P), ("pos", _P), ("mass", _P), ("cell_first", _P),
+                ("cell_count", _P), ("child", _P), ("com", _P), ("bmax", _P), ("bbox", _P),
+                ("mom", _P), ("bucket_cell", _P)]
+
+
+class Walk(ctypes.Structure):
+    _fields_ = [("n_cell", _I64), ("child", _P), ("com", _P), ("bmax", _P), ("bbox", _P),
+                ("n_roots", _I), ("roots", ctypes.c_int32 * 2), ("theta", _D), ("eps", _D),
+                ("L", _D), ("n_images", _I), ("n_sink", _I64), ("sink_cell", _P)]
+
+
 class TrainConfig(ctypes.Structure):
     _fields_ = [("epochs", _I), ("batch", _I), ("lr", ctypes.c_float),
                 ("lr_min", ctypes.c_float), ("beta1", ctypes.c_float),
@@ -145,6 +157,20 @@ def _declare():
     L.mgrav_autotune.argtypes = [_P, _P, _P, ctypes.c_char_p, _D, ctypes.POINTER(_I), _P]
     L.mgrav_set_launch_mode.restype = _I
     L.mgrav_set_launch_mode.argtypes = [_P, _I]
+    L.mgrav_tree_workspace_size.restype = _I
+    L.mgrav_tree_workspace_size.argtypes = [_I64, _I, _I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgrav_tree_build.restype = _I
+    L.mgrav_tree_build.argtypes = [_P, _I64, _P, _P, _P, _D, _I, _P, ctypes.c_size_t, _I64,
+                                   ctypes.POINTER(TreeDev), ctypes.POINTER(_I64),
+                                   ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
+    L.mgrav_lists_workspace_size.restype = _I
+    L.mgrav_lists_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgrav_lists_count.restype = _I
+    L.mgrav_lists_count.argtypes = [_P, ctypes.POINTER(Walk), _P, ctypes.c_size_t, _P, _P,
+                                    ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
+    L.mgrav_lists_fill.restype = _I
+    L.mgrav_lists_fill.argtypes = [_P, ctypes.POINTER(Walk), _P, ctypes.c_size_t, _P, _P, _P,
+                                   _P, _P, _P]
     L.mgrav_watchdog_poll.restype = _I
     L.mgrav_watchdog_poll.argtypes = [WATCHDOG_QUERY, _P, _D]
 
@@ -161,6 +187,8 @@ EXPORTS = (
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
     "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
     "mgrav_autotune", "mgrav_set_launch_mode", "mgrav_watchdog_poll",
+    "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_lists_workspace_size",
+    "mgrav_lists_count", "mgrav_lists_fill",
 )
 
 
@@ -229,6 +257,58 @@ class Lists:
     pc_src: np.ndarray
     pc_img: np.ndarray
     n_images: int
+
+
+@dataclasses.dataclass
+class DeviceTree:
+    """Tree (or two-tree forest) built on the device: torch tensors in the
+    layout of include/mgrav.h, plus the particles in tree order."""
+
+    perm: object
+    pos: object
+    mass: object
+    cell_first: object
+    cell_count: object
+    child: object
+    com: object
+    bmax: object
+    bbox: object
+    mom: object
+    bucket_cell: object
+    box_L: float
+    n_cell_first: int  # cells of the first tree (all cells for one tree)
+    grouped: bool
+
+    @property
+    def roots(self):
+        return (0, self.n_cell_first) if self.grouped else (0,)
+
+    @property
+    def n_bucket_first(self) -> int:
+        return (self.n_cell_first + 1) // 2
+
+    def to_host(self) -> "Tree":
+        f = {k: getattr(self, k).cpu().numpy() for k in
+             ("perm", "cell_first", "cell_count", "child", "com", "bmax", "bbox", "mom",
+              "bucket_cell")}
+        return Tree(**f, box_L=self.box_L)
+
+
+@dataclasses.dataclass
+class DeviceLists:
+    pp_off: object
+    pp_src: object
+    pp_img: object
+    pc_off: object
+    pc_src: object
+    pc_img: object
+    n_images: int
+    first_sink: int  # buckets before it have empty lists
+
+    def to_host(self) -> "Lists":
+        return Lists(*[getattr(self, k).cpu().numpy() for k in
+                       ("pp_off", "pp_src", "pp_img", "pc_off", "pc_src", "pc_img")],
+                     self.n_images)
 
 
 def tree_build(pos: np.ndarray, mass: np.ndarray, box_L: float, bucket: int = 16) -> Tree:
@@ -369,6 +449,133 @@ class Context:
         p.n_pp = int(lists.pp_off[-1])
         p.n_pc = int(lists.pc_off[-1])
         torch.cuda.synchronize(dev)
+        return keep, p
+
+    def tree_build(self, pos_dev, mass_dev, box_L: float, bucket: int = 16, group_dev=None,
+                   cap: Optional[int] = None):
+        """The tree (or, with ``group_dev``, the two-tree forest of Sec. 3.2)
+        built on the device from positions [n, 3] and masses [n] (float64
+        device tensors, input order).  Returns a DeviceTree of device
+        tensors trimmed to the cell count."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        n = int(pos_dev.shape[0])
+        pos_dev = pos_dev.contiguous()
+        mass_dev = mass_dev.contiguous()
+        caps = [cap] if cap else sorted({min(c, 2 * n + 2) for c in (max(64, n // 4), n // 2 + 64,
+                                                                     2 * n + 2)})
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        for k, cp in enumerate(caps):
+            sz = ctypes.c_size_t(0)
+            _check(_lib.mgrav_tree_workspace_size(n, int(bucket), int(cp), ctypes.byref(sz)))
+            ws = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
+            f64 = dict(dtype=torch.float64, device=dev)
+            out = dict(perm=torch.empty(n, dtype=torch.int64, device=dev),
+                       pos=torch.empty((n, 3), **f64), mass=torch.empty(n, **f64),
+                       cell_first=torch.empty(cp, dtype=torch.int64, device=dev),
+                       cell_count=torch.empty(cp, dtype=torch.int32, device=dev),
+                       child=torch.empty((cp, 2), dtype=torch.int32, device=dev),
+                       com=torch.empty((cp, 3), **f64), bmax=torch.empty(cp, **f64),
+                       bbox=torch.empty((cp, 6), **f64), mom=torch.empty((cp, 32), **f64),
+                       bucket_cell=torch.empty(cp, dtype=torch.int32, device=dev))
+            td = TreeDev(*[out[f].data_ptr() for f, _ in TreeDev._fields_])
+            nc, nb, nf = _I64(0), _I64(0), _I64(0)
+            st = _lib.mgrav_tree_build(self._h, n, _P(pos_dev.data_ptr()),
+                                       _P(mass_dev.data_ptr()),
+                                       _P(group_dev.data_ptr()) if group_dev is not None else None,
+                                       float(box_L), int(bucket), _P(ws.data_ptr()),
+                                       ctypes.c_size_t(ws.numel()), int(cp), ctypes.byref(td),
+                                       ctypes.byref(nc), ctypes.byref(nb), ctypes.byref(nf))
+            del ws
+            if st == OK:
+                break
+            msg = _lib.mgrav_last_error(self._h) or b""
+            if st != ERR_INVALID_ARG or b"capacity" not in msg or k == len(caps) - 1:
+                _check(st, self._h)
+        c, b = int(nc.value), int(nb.value)
+        trim = {f: (v if f in ("perm", "pos", "mass") else v[:(b if f == "bucket_cell" else c)])
+                for f, v in out.items()}
+        return DeviceTree(**trim, box_L=float(box_L), n_cell_first=int(nf.value),
+                          grouped=group_dev is not None)
+
+    def lists_build(self, dtree, theta: float, eps: float, sinks: str = "all",
+                    n_images: Optional[int] = None):
+        """Checklist walk on the device for the buckets of a DeviceTree
+        (``sinks='all'``) or of its second tree only (``'second'``, a forest);
+        the checklist holds every root of the tree.  Returns DeviceLists
+        whose offsets cover every bucket of the tree (buckets that are not
+        sinks get empty lists)."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        L = dtree.box_L
+        nimg = n_images if n_images is not None else (27 if L > 0 else 1)
+        nb = int(dtree.bucket_cell.shape[0])
+        first = 0
+        if sinks == "second":
+            if not dtree.grouped:
+                raise ValueError("sinks='second' needs a forest")
+            first = dtree.n_bucket_first
+        w = Walk()
+        w.n_cell = int(dtree.cell_first.shape[0])
+        w.child, w.com = dtree.child.data_ptr(), dtree.com.data_ptr()
+        w.bmax, w.bbox = dtree.bmax.data_ptr(), dtree.bbox.data_ptr()
+        roots = dtree.roots
+        w.n_roots = len(roots)
+        w.roots[0] = roots[0]
+        w.roots[1] = roots[1] if len(roots) > 1 else 0
+        w.theta, w.eps, w.L, w.n_images = float(theta), float(eps), float(L), int(nimg)
+        w.n_sink = nb - first
+        sink = dtree.bucket_cell[first:]
+        w.sink_cell = sink.data_ptr()
+        sz = ctypes.c_size_t(0)
+        _check(_lib.mgrav_lists_workspace_size(w.n_cell, w.n_sink, ctypes.byref(sz)))
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
+        pp_off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        pc_off = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        npp, npc = _I64(0), _I64(0)
+        _check(_lib.mgrav_lists_count(self._h, ctypes.byref(w), _P(ws.data_ptr()),
+                                      ctypes.c_size_t(ws.numel()), _P(pp_off[first:].data_ptr()),
+                                      _P(pc_off[first:].data_ptr()), ctypes.byref(npp),
+                                      ctypes.byref(npc)), self._h)
+        pp_src = torch.empty(max(1, npp.value), dtype=torch.int32, device=dev)
+        pp_img = torch.empty(max(1, npp.value), dtype=torch.uint8, device=dev)
+        pc_src = torch.empty(max(1, npc.value), dtype=torch.int32, device=dev)
+        pc_img = torch.empty(max(1, npc.value), dtype=torch.uint8, device=dev)
+        _check(_lib.mgrav_lists_fill(self._h, ctypes.byref(w), _P(ws.data_ptr()),
+                                     ctypes.c_size_t(ws.numel()), _P(pp_off[first:].data_ptr()),
+                                     _P(pc_off[first:].data_ptr()), _P(pp_src.data_ptr()),
+                                     _P(pp_img.data_ptr()), _P(pc_src.data_ptr()),
+                                     _P(pc_img.data_ptr())), self._h)
+        return DeviceLists(pp_off, pp_src[:npp.value], pp_img[:npp.value], pc_off,
+                           pc_src[:npc.value], pc_img[:npc.value], int(nimg), first)
+
+    def problem_device(self, dtree, dlists, eps: float, theta: float):
+        """A Problem over a DeviceTree and DeviceLists (no host copies);
+        returns (tensors to keep alive, Problem)."""
+        keep = dict(pos=dtree.pos, mass=dtree.mass, cell_first=dtree.cell_first,
+                    cell_count=dtree.cell_count, child=dtree.child, com=dtree.com,
+                    bbox=dtree.bbox, mom=dtree.mom, bucket_cell=dtree.bucket_cell,
+                    pp_off=dlists.pp_off, pp_src=dlists.pp_src, pp_img=dlists.pp_img,
+                    pc_off=dlists.pc_off, pc_src=dlists.pc_src, pc_img=dlists.pc_img)
+        torch = self._torch
+        one32 = torch.zeros(1, dtype=torch.int32, device=dtree.pos.device)
+        one8 = torch.zeros(1, dtype=torch.uint8, device=dtree.pos.device)
+        for k, z in (("pp_src", one32), ("pc_src", one32), ("pp_img", one8), ("pc_img", one8)):
+            if keep[k].numel() == 0:
+                keep[k] = z
+        p = Problem()
+        p.n = int(dtree.pos.shape[0])
+        p.eps, p.theta, p.box_L = float(eps), float(theta), float(dtree.box_L)
+        p.n_images = int(dlists.n_images)
+        p.n_cell = int(dtree.cell_first.shape[0])
+        p.n_bucket = int(dtree.bucket_cell.shape[0])
+        for name in ("pos", "mass", "cell_first", "cell_count", "child", "com", "bbox", "mom",
+                     "bucket_cell", "pp_off", "pp_src", "pp_img", "pc_off", "pc_src",
+                     "pc_img"):
+            setattr(p, name, keep[name].data_ptr())
+        p.n_pp = int(dlists.pp_src.numel())
+        p.n_pc = int(dlists.pc_src.numel())
         return keep, p
 
     def workspace_size(self, p: Problem) -> int:

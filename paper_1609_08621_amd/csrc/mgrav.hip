@@ -31,6 +31,7 @@
 #include <string>
 #include <thread>
 #include <utility>
+#include <vector>
 
 #include "../../include/mgrav.h"
 #include "internal.h"
@@ -2609,3 +2610,4 @@ mgrav_status mgrav_set_launch_mode(mgrav_ctx* c, int mode) {
 }  // extern "C"
 
 #include "mlp_api.inc"
+#include "tree_dev.inc"
