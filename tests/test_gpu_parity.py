@@ -415,26 +415,27 @@ def test_bad_list_entry_is_reported_not_dereferenced(mg_ctx):
 @pytest.mark.timeout(1200)
 def test_clustered_512_full_size_sampled(mg_ctx):
     """The 512^3 clustered set of one GPU's share: n = 2^27, the largest
-    count the PP entries' 27-bit particle index admits.  The device runs the
-    library's own host tree and lists (equal to the oracle's, tested on
-    smaller sets); the oracle builds its own tree and walks only the sampled
-    sink buckets (every k-th of about 13 million, plus the last bucket, which
-    holds particle n - 1).  Compared per input particle: all parts, then a
-    1 % active substep against the full run."""
+    count the PP entries' 27-bit particle index admits.  The device builds
+    the tree and walks the lists; the oracle builds its own tree (compared
+    in full: structure, boxes and bucket properties exactly) and walks only
+    the sampled sink buckets (every k-th of about 13 million, plus the last
+    bucket, which holds particle n - 1): their lists must be equal, and
+    every part of the force within the bar.  Then a 1 % active substep
+    against the full run."""
     import dataclasses
     mg, ctx = mg_ctx
     ps = workloads.make(5)
     n = ps.n
     assert n == 1 << 27
-    _case(f"clustered_512_full n={n}: host tree and lists")
-    tree = mg.tree_build(ps.pos, ps.mass, ps.box_L, 16)
-    lists = mg.lists_build(tree, 0.7, ps.eps)
-    pos_t, mass_t = ps.pos[tree.perm], ps.mass[tree.perm]
-    _case(f"clustered_512_full upload + bind (buckets={tree.n_bucket}, pp={lists.pp_src.size}, "
-          f"pc={lists.pc_src.size})")
-    tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
-    del lists
-    ctx.bind(p, tensors)
+    dev = torch.device("cuda", 0)
+    _case(f"clustered_512_full n={n}: device tree and lists")
+    td = ctx.tree_build(torch.from_numpy(ps.pos).to(dev), torch.from_numpy(ps.mass).to(dev),
+                        ps.box_L, 16)
+    dl = ctx.lists_build(td, 0.7, ps.eps)
+    print(f"  cells={td.cell_first.shape[0]} buckets={td.bucket_cell.shape[0]} "
+          f"pp={dl.pp_src.numel()} pc={dl.pc_src.numel()}", flush=True)
+    keep, p = ctx.problem_device(td, dl, ps.eps, 0.7)
+    ctx.bind(p, keep)
     acc, pot = ctx.outputs()
     _case("clustered_512_full compute all parts")
     ctx.compute(acc, pot)
@@ -444,46 +445,54 @@ def test_clustered_512_full_size_sampled(mg_ctx):
     print(f"  pp={st.n_pp_interactions} pc={st.n_pc_interactions} ms={st.ms_total:.1f}",
           flush=True)
     assert np.all(np.isfinite(a_full)) and np.all(np.isfinite(p_full))
-    a_in = np.empty_like(a_full)
-    a_in[tree.perm] = a_full
-    p_in = np.empty_like(p_full)
-    p_in[tree.perm] = p_full
-    perm_lib = tree.perm
-    del tree
 
-    _case("clustered_512_full oracle tree and sampled lists")
+    _case("clustered_512_full oracle tree against the device tree")
     to = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
-    assert np.array_equal(to.perm, perm_lib)
+    th = td.to_host()
+    for f in ("perm", "cell_first", "cell_count", "child", "bucket_cell", "bbox"):
+        assert np.array_equal(getattr(th, f), getattr(to, f)), f
+    leaf = to.child[:, 0] < 0
+    for f in ("com", "bmax", "mom"):
+        assert np.array_equal(getattr(th, f)[leaf], getattr(to, f)[leaf]), f
+    del th
     sel = np.unique(np.r_[np.arange(0, to.n_bucket, to.n_bucket // 96), to.n_bucket - 1])
     sub = dataclasses.replace(to, bucket_cell=np.ascontiguousarray(to.bucket_cell[sel]))
+    _case(f"clustered_512_full oracle lists of {sel.size} sampled buckets against the device's")
     lo = oracle.build_lists(sub, 0.7, ps.eps)
+    pp_off, pc_off = dl.pp_off.cpu().numpy(), dl.pc_off.cpu().numpy()
+    for k, b in enumerate(sel):
+        for off, src, img, o_off, o_src, o_img in (
+                (pp_off, dl.pp_src, dl.pp_img, lo.pp_off, lo.pp_src, lo.pp_img),
+                (pc_off, dl.pc_src, dl.pc_img, lo.pc_off, lo.pc_src, lo.pc_img)):
+            a0, a1 = int(off[b]), int(off[b + 1])
+            assert a1 - a0 == o_off[k + 1] - o_off[k]
+            assert np.array_equal(src[a0:a1].cpu().numpy(), o_src[o_off[k]:o_off[k + 1]])
+            assert np.array_equal(img[a0:a1].cpu().numpy(), o_img[o_off[k]:o_off[k + 1]])
     idx = np.concatenate([np.arange(sub.cell_first[c], sub.cell_first[c] + sub.cell_count[c])
                           for c in sub.bucket_cell])
     assert idx.max() == n - 1
-    who = to.perm[idx]
     pos_o, mass_o = ps.pos[to.perm], ps.mass[to.perm]
     for parts, name in ((mg.PART_PP | mg.PART_PC, "PP+PC"), (mg.PART_ALL, "ALL")):
         if parts != mg.PART_ALL:
             ctx.compute(acc, pot, parts)
             ctx.wait(300)
-            ag = np.empty_like(a_full)
-            ag[perm_lib] = acc.cpu().numpy().reshape(3, -1).T
-            ag = ag[who]
+            ag = acc.cpu().numpy().reshape(3, -1).T[idx]
         else:
-            ag = a_in[who]
+            ag = a_full[idx]
         ao, po = oracle.evaluate(sub, lo, pos_o, mass_o, ps.eps, parts)
         ao = ao[idx]
         rel = np.sqrt(np.sum((ag - ao) ** 2, 1) / np.sum(ao ** 2, 1))
         print(f"  {name}: {idx.size} particles of {sel.size} buckets: rms {np.sqrt(np.mean(rel ** 2)):.3e} "
               f"max {rel.max():.3e} p99 {np.quantile(rel, 0.99):.3e}", flush=True)
         assert np.sqrt(np.mean(rel ** 2)) < TOL_ACC
-        if name == "ALL":
-            pe = np.sqrt(np.sum((p_in[who] - po[idx]) ** 2) / np.sum(po[idx] ** 2))
+        if name != "ALL":
+            pot_tree = po[idx]  # the PP + PC potential: the scale of the periodic total
+        else:
+            pe = np.sqrt(np.sum((p_full[idx] - po[idx]) ** 2) / np.sum(pot_tree ** 2))
             print(f"  potential: global rel {pe:.3e}", flush=True)
             assert pe < TOL_POT
 
     _case("clustered_512_full 1% active substep against the full run")
-    dev = torch.device("cuda", 0)
     active = workloads.active_by_acceleration(np.linalg.norm(a_full, axis=1), 0.01)
     ctx.set_active(torch.from_numpy(active).to(dev))
     acc2 = torch.full((3 * n,), -5.0, dtype=torch.float32, device=dev)
