@@ -46,7 +46,7 @@ extern "C" {
 #endif
 
 #define MGRAV_VERSION_MAJOR 0
-#define MGRAV_VERSION_MINOR 2
+#define MGRAV_VERSION_MINOR 3
 
 /* Largest bucket (leaf) the device kernels accept; the paper's optimum
  * bucket size is about 16 (Sec. 3.1). */
@@ -243,6 +243,64 @@ mgrav_status mgrav_lists_fill(mgrav_ctx *ctx, const mgrav_walk *walk, void *work
                               uint8_t *pc_img);
 
 /* ------------------------------------------------------------------ */
+/* The persistent particle store of Sec. 3.4 and the steps of the      */
+/* hierarchical kick-drift-kick integrator of Sec. 3.2 (device).       */
+/* ------------------------------------------------------------------ */
+
+/* 28 bytes per particle: a position as three unsigned 32-bit integers,
+ * x = origin + q * scale per axis (periodic box: origin 0 and scale
+ * L / 2^32, so the integers wrap as the box does; open: a grid slightly
+ * larger than the particles' extent), the velocity as three floats, and
+ * one word with the rung (bits 0..7) and a group id (bits 8..31).  The
+ * arrays are device memory owned by the caller. */
+typedef struct {
+    uint32_t *q;      /* [n][3] */
+    float *vel;       /* [n][3] */
+    uint32_t *aux;    /* [n]    */
+    double origin[3];
+    double scale;     /* length of one integer step (> 0) */
+} mgrav_store;
+
+/* q = nearest grid point (ties to even) of pos [n][3] (device, double),
+ * modulo 2^32 when `periodic`, else INVALID_ARG if a point lies off the
+ * grid; vel [n][3] (device, nullable: zero) copied; aux cleared.  All the
+ * store calls are blocking and return INVALID_ARG for null pointers, n
+ * outside 1 .. 2^27, a non-finite origin or scale <= 0. */
+mgrav_status mgrav_store_encode(mgrav_ctx *ctx, int64_t n, const double *pos, const float *vel,
+                                int periodic, const mgrav_store *st);
+/* pos = origin + q * scale (device [n][3], double, one fused multiply-add
+ * per coordinate, as the evaluation reads pos_q; exact when the values fit
+ * 53 bits), vel copied when non-NULL. */
+mgrav_status mgrav_store_decode(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, double *pos,
+                                float *vel);
+/* out[k] = in[perm[k]] for every array of the store (the tree order of
+ * mgrav_tree_build's perm); separate output arrays. */
+mgrav_status mgrav_store_permute(mgrav_ctx *ctx, int64_t n, const mgrav_store *in,
+                                 const int64_t *perm, const mgrav_store *out);
+/* Drift every particle by dt: q += nearest integer of v dt / scale (exact
+ * integer arithmetic, wrapping when periodic; INVALID_ARG if an open-box
+ * coordinate leaves the grid). */
+mgrav_status mgrav_store_drift(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, double dt,
+                               int periodic);
+/* Half kick of the particles on rungs >= rung_lo: v += a dt_base / 2^(rung+1),
+ * acc [3][n] float SoA (device, as mgrav_compute writes it), in double and
+ * rounded to float once. */
+mgrav_status mgrav_store_kick(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, const float *acc,
+                              double dt_base, int rung_lo);
+/* New rungs of the particles on rungs >= rung_lo (those at the end of
+ * their step): the time-step criterion of Sec. 3.2, dt_i = eta
+ * sqrt(eps / |a_i|) (eta = 0.2 in the paper), gives the smallest rung l
+ * with dt_base / 2^l <= dt_i, clamped to [rung_floor, rung_max]
+ * (rung_floor: the shallowest rung whose step boundary is now). */
+mgrav_status mgrav_store_rungs(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, const float *acc,
+                               double eps, double eta, double dt_base, int rung_lo,
+                               int rung_floor, int rung_max);
+/* active[i] = 1 if rung >= rung_lo else 0 (device uint8 [n]; the mask of
+ * mgrav_set_active). */
+mgrav_status mgrav_store_active(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, int rung_lo,
+                                uint8_t *active);
+
+/* ------------------------------------------------------------------ */
 /* Device-side evaluation.                                             */
 /* ------------------------------------------------------------------ */
 
@@ -251,8 +309,8 @@ mgrav_status mgrav_lists_fill(mgrav_ctx *ctx, const mgrav_walk *walk, void *work
  * mgrav_bind or mgrav_destroy).  Scalars are host values. */
 typedef struct {
     int64_t n;               /* particles (1 .. MGRAV_MAX_PARTICLES)          */
-    const double *pos;       /* [n][3] positions, tree order                  */
-    const double *mass;      /* [n] masses (> 0)                              */
+    const double *pos;       /* [n][3] positions, tree order (or pos_q below) */
+    const double *mass;      /* [n] masses (> 0), or NULL (mass_uniform)      */
     double eps;              /* Plummer softening (> 0)                       */
     double theta;            /* opening angle the lists were built with (> 0) */
     double box_L;            /* periodic box side; 0 = open boundaries         */
@@ -274,6 +332,14 @@ typedef struct {
     const uint8_t *pc_img;     /* [n_pc] image id                             */
     int64_t n_pp;              /* = pp_off[n_bucket] (host copy)              */
     int64_t n_pc;              /* = pc_off[n_bucket] (host copy)              */
+    /* Positions from the integer coordinates of a particle store (Sec. 3.4)
+     * instead of `pos` (exactly one of the two is non-NULL):
+     * x = q_origin + pos_q * q_scale per axis, [n][3] in tree order. */
+    const uint32_t *pos_q;
+    double q_origin[3];
+    double q_scale;
+    /* With mass == NULL every particle has this mass (> 0). */
+    double mass_uniform;
 } mgrav_problem;
 
 /* Device workspace the caller must provide to mgrav_bind for `p`:

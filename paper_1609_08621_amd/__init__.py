@@ -53,7 +53,14 @@ class Problem(ctypes.Structure):
         ("cell_count", _P), ("child", _P), ("com", _P), ("bbox", _P), ("mom", _P),
         ("bucket_cell", _P), ("pp_off", _P), ("pp_src", _P), ("pp_img", _P), ("pc_off", _P),
         ("pc_src", _P), ("pc_img", _P), ("n_pp", _I64), ("n_pc", _I64),
+        ("pos_q", _P), ("q_origin", _D * 3), ("q_scale", _D), ("mass_uniform", _D),
     ]
+
+
+class Store(ctypes.Structure):
+    """mgrav_store: device arrays q [n][3] uint32, vel [n][3] float32,
+    aux [n] uint32 and the grid (x = origin + q * scale)."""
+    _fields_ = [("q", _P), ("vel", _P), ("aux", _P), ("origin", _D * 3), ("scale", _D)]
 
 
 class EwaldConfig(ctypes.Structure):
@@ -171,6 +178,21 @@ def _declare():
     L.mgrav_lists_fill.restype = _I
     L.mgrav_lists_fill.argtypes = [_P, ctypes.POINTER(Walk), _P, ctypes.c_size_t, _P, _P, _P,
                                    _P, _P, _P]
+    SP = ctypes.POINTER(Store)
+    L.mgrav_store_encode.restype = _I
+    L.mgrav_store_encode.argtypes = [_P, _I64, _P, _P, _I, SP]
+    L.mgrav_store_decode.restype = _I
+    L.mgrav_store_decode.argtypes = [_P, _I64, SP, _P, _P]
+    L.mgrav_store_permute.restype = _I
+    L.mgrav_store_permute.argtypes = [_P, _I64, SP, _P, SP]
+    L.mgrav_store_drift.restype = _I
+    L.mgrav_store_drift.argtypes = [_P, _I64, SP, _D, _I]
+    L.mgrav_store_kick.restype = _I
+    L.mgrav_store_kick.argtypes = [_P, _I64, SP, _P, _D, _I]
+    L.mgrav_store_rungs.restype = _I
+    L.mgrav_store_rungs.argtypes = [_P, _I64, SP, _P, _D, _D, _D, _I, _I, _I]
+    L.mgrav_store_active.restype = _I
+    L.mgrav_store_active.argtypes = [_P, _I64, SP, _I, _P]
     L.mgrav_watchdog_poll.restype = _I
     L.mgrav_watchdog_poll.argtypes = [WATCHDOG_QUERY, _P, _D]
 
@@ -188,7 +210,9 @@ EXPORTS = (
     "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
     "mgrav_autotune", "mgrav_set_launch_mode", "mgrav_watchdog_poll",
     "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_lists_workspace_size",
-    "mgrav_lists_count", "mgrav_lists_fill",
+    "mgrav_lists_count", "mgrav_lists_fill", "mgrav_store_encode", "mgrav_store_decode",
+    "mgrav_store_permute", "mgrav_store_drift", "mgrav_store_kick", "mgrav_store_rungs",
+    "mgrav_store_active",
 )
 
 
@@ -257,6 +281,35 @@ class Lists:
     pc_src: np.ndarray
     pc_img: np.ndarray
     n_images: int
+
+
+@dataclasses.dataclass
+class ParticleStore:
+    """Device arrays of the 28-byte particle store (mgrav_store): q [n, 3]
+    (uint32 bits held in int32), vel [n, 3] float32, aux [n] (rung in bits
+    0..7, group id above); x = origin + q * scale."""
+
+    q: object
+    vel: object
+    aux: object
+    origin: tuple
+    scale: float
+
+    @property
+    def n(self) -> int:
+        return int(self.q.shape[0])
+
+    def c(self) -> "Store":
+        s = Store()
+        s.q, s.vel, s.aux = self.q.data_ptr(), self.vel.data_ptr(), self.aux.data_ptr()
+        for k in range(3):
+            s.origin[k] = self.origin[k]
+        s.scale = self.scale
+        return s
+
+    @property
+    def rung(self):
+        return self.aux & 0xff
 
 
 @dataclasses.dataclass
@@ -549,6 +602,76 @@ class Context:
                                      _P(pc_img.data_ptr())), self._h)
         return DeviceLists(pp_off, pp_src[:npp.value], pp_img[:npp.value], pc_off,
                            pc_src[:npc.value], pc_img[:npc.value], int(nimg), first)
+
+    def _sync_in(self):
+        """Inputs produced on torch's current stream come before the
+        context's own work."""
+        torch = self._torch
+        self.stream.wait_stream(torch.cuda.current_stream(torch.device("cuda", self.device)))
+
+    # ---- particle store (Sec. 3.4) and integrator steps (Sec. 3.2) ----
+    def store_alloc(self, n: int, origin, scale: float) -> "ParticleStore":
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        return ParticleStore(torch.zeros((n, 3), dtype=torch.int32, device=dev),
+                             torch.zeros((n, 3), dtype=torch.float32, device=dev),
+                             torch.zeros(n, dtype=torch.int32, device=dev),
+                             tuple(float(o) for o in origin), float(scale))
+
+    def store_encode(self, st: "ParticleStore", pos_dev, vel_dev=None, periodic: bool = True):
+        self._sync_in()
+        s = st.c()
+        _check(_lib.mgrav_store_encode(self._h, st.n, _P(pos_dev.contiguous().data_ptr()),
+                                       _P(vel_dev.contiguous().data_ptr()) if vel_dev is not None
+                                       else None, int(bool(periodic)), ctypes.byref(s)), self._h)
+
+    def store_decode(self, st: "ParticleStore", with_vel: bool = False):
+        self._sync_in()
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        pos = torch.empty((st.n, 3), dtype=torch.float64, device=dev)
+        vel = torch.empty((st.n, 3), dtype=torch.float32, device=dev) if with_vel else None
+        s = st.c()
+        _check(_lib.mgrav_store_decode(self._h, st.n, ctypes.byref(s), _P(pos.data_ptr()),
+                                       _P(vel.data_ptr()) if vel is not None else None), self._h)
+        return (pos, vel) if with_vel else pos
+
+    def store_permute(self, st: "ParticleStore", perm_dev) -> "ParticleStore":
+        out = self.store_alloc(st.n, st.origin, st.scale)
+        self._sync_in()
+        a, b = st.c(), out.c()
+        _check(_lib.mgrav_store_permute(self._h, st.n, ctypes.byref(a), _P(perm_dev.data_ptr()),
+                                        ctypes.byref(b)), self._h)
+        return out
+
+    def store_drift(self, st: "ParticleStore", dt: float, periodic: bool = True):
+        self._sync_in()
+        s = st.c()
+        _check(_lib.mgrav_store_drift(self._h, st.n, ctypes.byref(s), float(dt),
+                                      int(bool(periodic))), self._h)
+
+    def store_kick(self, st: "ParticleStore", acc_dev, dt_base: float, rung_lo: int):
+        self._sync_in()
+        s = st.c()
+        _check(_lib.mgrav_store_kick(self._h, st.n, ctypes.byref(s), _P(acc_dev.data_ptr()),
+                                     float(dt_base), int(rung_lo)), self._h)
+
+    def store_rungs(self, st: "ParticleStore", acc_dev, eps: float, eta: float, dt_base: float,
+                    rung_lo: int, rung_floor: int, rung_max: int):
+        self._sync_in()
+        s = st.c()
+        _check(_lib.mgrav_store_rungs(self._h, st.n, ctypes.byref(s), _P(acc_dev.data_ptr()),
+                                      float(eps), float(eta), float(dt_base), int(rung_lo),
+                                      int(rung_floor), int(rung_max)), self._h)
+
+    def store_active(self, st: "ParticleStore", rung_lo: int):
+        self._sync_in()
+        torch = self._torch
+        act = torch.empty(st.n, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        s = st.c()
+        _check(_lib.mgrav_store_active(self._h, st.n, ctypes.byref(s), int(rung_lo),
+                                       _P(act.data_ptr())), self._h)
+        return act
 
     def problem_device(self, dtree, dlists, eps: float, theta: float):
         """A Problem over a DeviceTree and DeviceLists (no host copies);

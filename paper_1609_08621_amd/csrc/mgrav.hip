@@ -184,12 +184,40 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
 // ---------------------------------------------------------------------
 // Staging (mgrav_bind)
 // ---------------------------------------------------------------------
+// Where particle positions come from: double coordinates, or the integer
+// coordinates of the particle store (x = origin + q * scale per axis).
+struct PosIn {
+    const double* pos;  // [n][3], or NULL
+    const uint32_t* q;  // [n][3] when pos is NULL
+    double ox, oy, oz, scale;
+};
+
+__device__ __forceinline__ void load_pos(const PosIn& in, int64_t i, double& x, double& y,
+                                         double& z) {
+    if (in.pos) {
+        x = in.pos[3 * i];
+        y = in.pos[3 * i + 1];
+        z = in.pos[3 * i + 2];
+    } else {
+        // one fused multiply-add, as the store's decode: the tree built from
+        // decoded positions and the staging see the same values
+        x = fma(double(in.q[3 * i]), in.scale, in.ox);
+        y = fma(double(in.q[3 * i + 1]), in.scale, in.oy);
+        z = fma(double(in.q[3 * i + 2]), in.scale, in.oz);
+    }
+}
+
+PosIn pos_in(const mgrav_problem& p) {
+    return PosIn{p.pos, p.pos_q, p.q_origin[0], p.q_origin[1], p.q_origin[2], p.q_scale};
+}
+
 struct StageArgs {
     int64_t n, n_cell, n_bucket, n_pp, n_pc;
     int n_images;
     double L, eps;
-    const double* __restrict__ pos;
-    const double* __restrict__ mass;
+    PosIn pin;
+    const double* __restrict__ mass;  // or NULL: every mass is mass_uniform
+    double mass_uniform;
     const int64_t* __restrict__ cell_first;
     const int32_t* __restrict__ cell_count;
     const int32_t* __restrict__ child;
@@ -336,8 +364,9 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
         if (sl == 0) atomicOr(&a.ctl->err, kErrTree);
     } else if (sl < ci.count) {
         const int64_t p = ci.first + sl;
-        const double x = a.pos[3 * p], y = a.pos[3 * p + 1], z = a.pos[3 * p + 2];
-        const double m = a.mass[p];
+        double x, y, z;
+        load_pos(a.pin, p, x, y, z);
+        const double m = a.mass ? a.mass[p] : a.mass_uniform;
         if (!(isfinite(x) && isfinite(y) && isfinite(z) && m > 0.0 && isfinite(m)))
             atomicOr(&a.ctl->err, kErrParticle);
         a.pdat[p] = make_float4(float(x - ci.cx), float(y - ci.cy), float(z - ci.cz), float(m));
@@ -1008,7 +1037,7 @@ static_assert(kNumVariants == 6, "interact_kernel and launch_interact list every
 // ---------------------------------------------------------------------
 struct EwaldArgs {
     int64_t n;
-    const double* __restrict__ pos;
+    PosIn pin;
     const double* __restrict__ mom;   // root = cell 0
     const double* __restrict__ com;   // root = cell 0
     const uint8_t* __restrict__ active;
@@ -1260,9 +1289,11 @@ __device__ __forceinline__ void ewald_particle(const EwaldArgs& a, int64_t i, do
                                                double2* ew_lds) {
     const TableRec rec{a.table};
     const double invL = 1.0 / a.L;
-    const double rx = (a.pos[3 * i] - a.com[0]) * invL;
-    const double ry = (a.pos[3 * i + 1] - a.com[1]) * invL;
-    const double rz = (a.pos[3 * i + 2] - a.com[2]) * invL;
+    double xi0, xi1, xi2;
+    load_pos(a.pin, i, xi0, xi1, xi2);
+    const double rx = (xi0 - a.com[0]) * invL;
+    const double ry = (xi1 - a.com[1]) * invL;
+    const double rz = (xi2 - a.com[2]) * invL;
     double phi = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
     const int R = a.real_layers;
     // exp(-alpha^2 |r - n|^2) of the 27 near images as products of per-axis
@@ -1573,6 +1604,7 @@ struct mgrav_ctx {
     int graph_error = 0;          // the HIP error that made it fail
     bool direct = false;          // MGRAV_LAUNCH_DIRECT chosen: no graphs
     Control* host_ctl = nullptr;  // pinned
+    int* store_err = nullptr;     // pinned: error words of the particle-store kernels
     MlpState mlp;
 };
 
@@ -1669,8 +1701,9 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.n_images = p.n_images;
     a.L = p.box_L;
     a.eps = p.eps;
-    a.pos = p.pos;
+    a.pin = pos_in(p);
     a.mass = p.mass;
+    a.mass_uniform = p.mass_uniform;
     a.cell_first = p.cell_first;
     a.cell_count = p.cell_count;
     a.child = p.child;
@@ -1708,8 +1741,16 @@ mgrav_status check_problem(mgrav_ctx* c, const mgrav_problem* p) {
     if (p->box_L < 0.0 || !std::isfinite(p->box_L))
         return fail(c, MGRAV_ERR_INVALID_ARG, "bad box_L");
     if (p->n_pp < 0 || p->n_pc < 0) return fail(c, MGRAV_ERR_INVALID_ARG, "negative list size");
-    if (!p->pos || !p->mass || !p->cell_first || !p->cell_count || !p->child || !p->com ||
-        !p->bbox || !p->mom || !p->bucket_cell || !p->pp_off || !p->pc_off)
+    if (!p->pos == !p->pos_q)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "give exactly one of pos and pos_q");
+    if (p->pos_q && (!(p->q_scale > 0.0) || !std::isfinite(p->q_scale) ||
+                     !std::isfinite(p->q_origin[0]) || !std::isfinite(p->q_origin[1]) ||
+                     !std::isfinite(p->q_origin[2])))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "pos_q needs a finite origin and scale > 0");
+    if (!p->mass && (!(p->mass_uniform > 0.0) || !std::isfinite(p->mass_uniform)))
+        return fail(c, MGRAV_ERR_INVALID_ARG, "mass NULL needs mass_uniform > 0");
+    if (!p->cell_first || !p->cell_count || !p->child || !p->com || !p->bbox || !p->mom ||
+        !p->bucket_cell || !p->pp_off || !p->pc_off)
         return fail(c, MGRAV_ERR_INVALID_ARG, "null device pointer in problem");
     if ((p->n_pp > 0 && (!p->pp_src || !p->pp_img)) || (p->n_pc > 0 && (!p->pc_src || !p->pc_img)))
         return fail(c, MGRAV_ERR_INVALID_ARG, "null list pointer");
@@ -1784,7 +1825,8 @@ mgrav_status mgrav_create(int device, void* hip_stream, mgrav_ctx** out) {
         hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
         hipEventCreate(&c->ev_e1) != hipSuccess || hipEventCreate(&c->ev_e0) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->host_ctl), sizeof(Control)) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&c->host_ctl), sizeof(Control)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->store_err), 64) != hipSuccess) {
         mgrav_destroy(c);
         return fail(nullptr, MGRAV_ERR_DEVICE, "event / pinned allocation failed");
     }
@@ -1806,6 +1848,7 @@ void mgrav_destroy(mgrav_ctx* c) {
     if (c->ev_e0) (void)hipEventDestroy(c->ev_e0);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    if (c->store_err) (void)hipHostFree(c->store_err);
     delete c;
 }
 
@@ -1968,7 +2011,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
         SurrogateArgs& g = L->sg;
         const MlpLayoutT& ml = c->mlp.lay;
         g.n = p.n;
-        g.pos = p.pos;
+        g.pin = pos_in(p);
         g.active = c->active;
         g.cells = reinterpret_cast<const double*>(c->mlp.ws + ml.cells);
         g.ncell = c->ewald.top_cells;
@@ -1995,7 +2038,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     if (L->ewald == MGRAV_EWALD_EXACT || judge) {
         EwaldArgs& e = L->e;
         e.n = p.n;
-        e.pos = p.pos;
+        e.pin = pos_in(p);
         e.mom = p.mom;
         e.com = p.com;
         e.active = c->active;
@@ -2611,3 +2654,4 @@ mgrav_status mgrav_set_launch_mode(mgrav_ctx* c, int mode) {
 
 #include "mlp_api.inc"
 #include "tree_dev.inc"
+#include "store.inc"

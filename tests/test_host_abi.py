@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(mg.EXPORTS)
-    assert mg.version() == 2
+    assert mg.version() == 3
 
 
 def test_status_strings():
@@ -136,7 +136,8 @@ def test_binding_structs_match_the_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     pairs = [("mgrav_problem", mg.Problem), ("mgrav_ewald", mg.EwaldConfig),
-             ("mgrav_stats", mg.Stats), ("mgrav_train_cfg", mg.TrainConfig)]
+             ("mgrav_stats", mg.Stats), ("mgrav_train_cfg", mg.TrainConfig),
+             ("mgrav_tree_dev", mg.TreeDev), ("mgrav_walk", mg.Walk), ("mgrav_store", mg.Store)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mgrav.h"',
              "int main(void) {"]
     for cname, cls in pairs:
@@ -184,3 +185,20 @@ def test_watchdog_times_out_on_a_query_that_never_completes():
 
     assert mg.watchdog_poll(lambda: -1, 5.0) == mg.ERR_DEVICE
     assert mg._lib.mgrav_watchdog_poll(mg.WATCHDOG_QUERY(), None, 1.0) == mg.ERR_INVALID_ARG
+
+
+def test_integrator_schedule_matches_the_oracle():
+    """The device integrator's host-side schedule (which rungs end a step at
+    each substep boundary) is the oracle's."""
+    from oracle import kdk
+    from paper_1609_08621_amd import kdk as dkdk
+    for R in range(0, 7):
+        assert [dkdk.boundary_rung(k, R) for k in range((1 << R) + 1)] == \
+            [kdk.boundary_rung(k, R) for k in range((1 << R) + 1)]
+
+
+def test_store_calls_refuse_bad_arguments_on_the_host():
+    st = mg.Store()
+    assert mg._lib.mgrav_store_encode(None, 10, None, None, 1, ctypes.byref(st)) == \
+        mg.ERR_INVALID_ARG
+    assert mg._lib.mgrav_store_drift(None, 10, ctypes.byref(st), 0.1, 1) == mg.ERR_INVALID_ARG
