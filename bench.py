@@ -48,6 +48,9 @@ def parse():
                     help="config 5: about this many sink buckets in the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle (CPU baseline; config 5: the sampled parity)")
+    ap.add_argument("--no-kdk", action="store_true",
+                    help="config 5: skip the integrator leg (one timed KDK base step)")
+    ap.add_argument("--kdk-rungs", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep PP + PC kernel variant 0 instead of timing all variants first")
     ap.add_argument("--ewald-study", action="store_true",
@@ -416,9 +419,15 @@ def substeps(args):
     ps = workloads.make(5)
     log(f"{cfg.name}: n={ps.n} generated in {time.perf_counter() - t0:.1f}s")
     n, eps = ps.n, ps.eps
+    m_uniform = float(ps.mass[0])
     dev = torch.device("cuda", 0)
     ctx = mg.Context(0)
-    pos_in = torch.from_numpy(ps.pos).to(dev)
+    # positions on the 2^32 grid of the particle store (Sec. 3.4): every
+    # leg below sees the same values, whether it reads the store's integers
+    # or their decoded doubles
+    store = ctx.store_alloc(n, (0.0, 0.0, 0.0), 1.0 / 2 ** 32)
+    ctx.store_encode(store, torch.from_numpy(ps.pos).to(dev), None, True)
+    pos_in = ctx.store_decode(store)
     mass_in = torch.from_numpy(ps.mass).to(dev)
     del ps
     torch.cuda.synchronize()
@@ -436,7 +445,9 @@ def substeps(args):
         prep["lists_s"] = time.perf_counter() - t0
         if rep == 0:
             del lists
-    del pos_in, mass_in
+    del mass_in
+    del pos_in
+    store = ctx.store_permute(store, tree.perm)
     n_cell, n_bucket = int(tree.cell_first.shape[0]), int(tree.bucket_cell.shape[0])
     log(f"device tree: {n_cell} cells, {n_bucket} buckets in {prep['tree_s']:.2f}s; lists: "
         f"{lists.pp_src.numel()} PP and {lists.pc_src.numel()} PC entries in "
@@ -566,6 +577,38 @@ def substeps(args):
             f"{row['interactions_per_s']:.3e} interactions/s, {row['particles_per_s']:.3e} "
             f"particles/s, kernel {row['kernel_tflops']:.1f} TFLOP/s, Ewald {ewald_row}")
     ctx.set_active(None)
+
+    # the particle store (Sec. 3.4): the same substeps reading positions as
+    # the store's 32-bit integers and equal masses without an array
+    store_rows = []
+    tensors_q, prob_q = ctx.problem_device(tree, lists, eps, cfg.theta)
+    prob_q.pos, prob_q.pos_q, prob_q.q_scale = None, store.q.data_ptr(), store.scale
+    prob_q.mass, prob_q.mass_uniform = None, m_uniform
+    tensors_q["q"] = store.q
+    for frac in (1.0, 0.01):
+        mask = None if frac == 1.0 else torch.from_numpy(
+            workloads.active_by_acceleration(amag, frac)).to(dev)
+        ms = {}
+        for label, (pr, te) in (("double", (prob, tensors)), ("store", (prob_q, tensors_q))):
+            def qstep():
+                ctx.bind(pr, te, ws)
+                ctx.set_ewald(**ew_cfg)
+                ctx.set_active(mask)
+                ctx.compute(acc, pot)
+                return ctx.wait(300.0)
+            qstep()
+            reps = 3 if frac == 1.0 else 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                qstep()
+            ms[label] = 1e3 * (time.perf_counter() - t0) / reps
+        store_rows.append({"active_fraction": frac, "ms_per_step_double_positions": ms["double"],
+                           "ms_per_step_store_positions": ms["store"]})
+        log(f"store: active {frac:.0%}: double positions {ms['double']:.2f} ms, store "
+            f"{ms['store']:.2f} ms per step")
+    ctx.set_active(None)
+    del tensors_q, prob_q
+
     st, flops, k_ms, steps = head
     achieved = flops / (k_ms * 1e-3) / 1e12
     kname = (f"k_interact<{tuned['pp_chunk']}, {tuned['waves_per_simd']}, "
@@ -611,6 +654,10 @@ def substeps(args):
                             "copy-calibrated)",
         },
         "substeps": rows,
+        "store_positions": {
+            "note": "positions read as the 28-byte store's 32-bit integers (12 B per particle, "
+                    "equal masses without an array) against double positions + masses (32 B)",
+            "rows": store_rows},
         "ewald": ewald_info,
         "device_prep_seconds": {"tree": prep["tree_s"], "lists": prep["lists_s"],
                                 "cells": n_cell, "buckets": n_bucket,
@@ -626,9 +673,52 @@ def substeps(args):
         out["cpu_baseline"] = cpu_baseline_sample(sample, pos_t, mass_t, eps, a_sample,
                                                   p_sample, st.n_pp_interactions +
                                                   st.n_pc_interactions)
+    if not args.no_kdk:
+        del tensors, prob, ws, lists, tree
+        torch.cuda.empty_cache()
+        out["kdk"] = kdk_leg(ctx, store, m_uniform, eps, cfg, amag, args.kdk_rungs)
     ctx.close()
     out["bench_seconds"] = time.perf_counter() - t_all
     print(json.dumps(out), flush=True)
+
+
+def kdk_leg(ctx, store, m_uniform, eps, cfg, amag, rung_max):
+    """One base step of the hierarchical KDK integrator (Sec. 3.2) on the
+    whole set, from rest, every force on the device tree, walk and PP + PC
+    + Ewald path; the base step is 2^(R-1) times the first percentile of
+    the particles' time steps, so the deepest rung holds about 1 % (their
+    substeps take the fixed and very active trees)."""
+    import numpy as np
+    import torch
+
+    from paper_1609_08621_amd.kdk import Integrator
+    dti = 0.2 * np.sqrt(eps / np.maximum(amag, 1e-300))
+    dt_base = float(np.quantile(dti, 0.01)) * (1 << (rung_max - 1))
+    pos = ctx.store_decode(store)
+    vel = torch.zeros_like(pos, dtype=torch.float32)
+    t0 = time.perf_counter()
+    it = Integrator(ctx, pos, vel, m_uniform, eps, cfg.theta, 1.0, dt_base, rung_max)
+    del pos, vel
+    it.start()
+    t_start = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    it.base_step()
+    t_step = time.perf_counter() - t0
+    rungs = np.bincount(it.store.rung.cpu().numpy(), minlength=rung_max + 1)
+    subs = [{"boundary": k, "rung_lo": lo, "active": n, "dual_tree": d, "seconds": sec}
+            for (k, lo, n, d), sec in zip(it.log, it.seconds)]
+    updates = sum(n for (_, _, n, _) in it.log)
+    log(f"kdk: base step {dt_base:.3e} of 2^{rung_max} substeps in {t_step:.2f}s "
+        f"({updates} particle updates), rungs {rungs.tolist()}, substeps "
+        f"{[(s['active'], s['dual_tree'], round(s['seconds'], 3)) for s in subs]}")
+    del it
+    torch.cuda.empty_cache()
+    return {"workload": f"{cfg.name} from rest, rungs 0..{rung_max}, dt_base {dt_base:.4e}",
+            "seconds_first_force": t_start, "seconds_base_step": t_step,
+            "particle_updates_per_s": updates / t_step, "rungs_after": rungs.tolist(),
+            "substeps": subs,
+            "note": "a substep = drift, device tree (both trees below 5 % active), lists, "
+                    "bind, PP + PC + Ewald for the active particles, kick and new rungs"}
 
 
 def cpu_baseline_sample(sample, pos_t, mass_t, eps, a_gpu, p_gpu, n_int_step):

@@ -21,7 +21,7 @@ base step, the opening half kick of their next step.
 """
 from __future__ import annotations
 
-import ctypes
+import time
 from typing import Optional
 
 
@@ -58,7 +58,8 @@ class Integrator:
         self.acc = torch.zeros(3 * self.n, dtype=torch.float32, device=self.dev)
         self.pot = torch.zeros(self.n, dtype=torch.float32, device=self.dev)
         self.mass_dev = torch.full((self.n,), self.mass, dtype=torch.float64, device=self.dev)
-        self.log = []  # (boundary, rung_lo, active, dual tree)
+        self.log = []  # (boundary, rung_lo, active, dual tree) per substep
+        self.seconds = []  # wall time per substep (every call blocks)
 
     # ---- one force computation -------------------------------------------------
     def _reorder(self, perm):
@@ -108,23 +109,24 @@ class Integrator:
         self.ctx.store_rungs(self.store, self.acc, self.eps, self.eta, self.dt, 0, 0, self.R)
 
     def base_step(self):
-        ctx, st = self.ctx, None
+        ctx = self.ctx
         nsub = 1 << self.R
         tau = self.dt / nsub
         ctx.store_kick(self.store, self.acc, self.dt, 0)
         for k in range(nsub):
+            t0 = time.perf_counter()
             ctx.store_drift(self.store, tau, self.periodic)
             k1 = k + 1
             lo = boundary_rung(k1, self.R)
             n_act, dual = self.forces(lo)
-            self.log.append((k1, lo, n_act, dual))
-            if n_act == 0:
-                continue
-            ctx.store_kick(self.store, self.acc, self.dt, lo)
-            ctx.store_rungs(self.store, self.acc, self.eps, self.eta, self.dt, lo, lo, self.R)
-            if k1 < nsub:
+            if n_act > 0:
                 ctx.store_kick(self.store, self.acc, self.dt, lo)
-        return st
+                ctx.store_rungs(self.store, self.acc, self.eps, self.eta, self.dt, lo, lo,
+                                self.R)
+                if k1 < nsub:
+                    ctx.store_kick(self.store, self.acc, self.dt, lo)
+            self.log.append((k1, lo, n_act, dual))
+            self.seconds.append(time.perf_counter() - t0)
 
     # ---- state in input order ------------------------------------------------------
     def state(self):

@@ -186,3 +186,33 @@ def test_kdk_periodic_lattice_matches_the_oracle(mg_ctx):
     dv = np.abs(vel_d - so.vel).max() / np.sqrt(np.mean(so.vel.astype(np.float64) ** 2))
     print(f"  max |dx| {d.max():.3e}, max |dv|/v_rms {dv:.3e}", flush=True)
     assert d.max() < 1e-6 and dv < 1e-4
+
+
+def test_store_positions_give_identical_forces(mg_ctx):
+    """The 64^3 lattice on the 2^32 grid of the unit box: the evaluation
+    reading positions from the store (12 bytes, equal masses without an
+    array) gives the same bits as reading the decoded doubles."""
+    mg, ctx = mg_ctx
+    ps = workloads.make(2)
+    origin, scale = (0.0, 0.0, 0.0), 1.0 / 2 ** 32
+    _case(f"store positions vs doubles, lattice_64 n={ps.n}")
+    st = ctx.store_alloc(ps.n, origin, scale)
+    ctx.store_encode(st, _dev(ps.pos), None, True)
+    pos = ctx.store_decode(st)
+    mass = torch.full((ps.n,), ps.mass[0], dtype=torch.float64, device=pos.device)
+    td = ctx.tree_build(pos, mass, 1.0, 16)
+    dl = ctx.lists_build(td, 0.7, ps.eps)
+    st = ctx.store_permute(st, td.perm)
+    out = []
+    for use_store in (False, True):
+        keep, p = ctx.problem_device(td, dl, ps.eps, 0.7)
+        if use_store:
+            p.pos, p.pos_q, p.q_scale = None, st.q.data_ptr(), scale
+            p.mass, p.mass_uniform = None, float(ps.mass[0])
+            keep["q"] = st.q
+        ctx.bind(p, keep)
+        acc, pot = ctx.outputs()
+        ctx.compute(acc, pot)
+        ctx.wait(120)
+        out.append((acc.cpu().numpy(), pot.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
