@@ -76,6 +76,15 @@ def _declare(L):
                                         _P]
     L.orc_lists_fill_roots.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _I, _P, _P,
                                        _P, _P, _P, _P, _P]
+    L.orc_fmm_walk.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _I, _I, _P, _P,
+                               _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_fmm_local.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _P, _P, _P, _P]
+    L.orc_fmm_l2p.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_fmm_m2l_point.argtypes = [_P, _D, _I, _P, _P, _D, _P]
+    L.orc_fmm_l2l_point.argtypes = [_P, _P, _P]
+    L.orc_fmm_l2p_point.argtypes = [_P, _P, _P]
+    L.orc_eval_sub.argtypes = [_I64, _P, _P, _D, _D, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P,
+                               _P, _P, _P, _I64, _P, _I, _D, _I, _I, _P, _P]
     L.orc_lists_count.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P]
     L.orc_lists_fill.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _D, _D, _I, _P, _P, _P,
                                  _P, _P, _P]
@@ -265,6 +274,120 @@ def evaluate(tree: Tree, lists: Lists, pos_tree: np.ndarray, mass_tree: np.ndarr
                    0 if sel is None else sel.shape[0], _p(sel), int(parts),
                    float(ew["alpha"]), int(ew["rmax"]), int(ew["h2max"]), _p(acc), _p(pot))
     return acc, pot
+
+
+@dataclasses.dataclass
+class FmmLists:
+    """Lists of the fast-multipole walk: per bucket PP entries (source
+    leaf, image, sub = 0 for the whole leaf or k + 1 for its k-th
+    particle) and PC entries; per cell CC / CP entries (source cell, or ~p
+    for tree-order particle p) whose expansions go into the cell's local
+    expansion."""
+
+    pp_off: np.ndarray
+    pp_src: np.ndarray
+    pp_img: np.ndarray
+    pp_sub: np.ndarray
+    pc_off: np.ndarray
+    pc_src: np.ndarray
+    pc_img: np.ndarray
+    cc_off: np.ndarray
+    cc_src: np.ndarray
+    cc_img: np.ndarray
+    n_images: int
+
+
+def build_fmm_lists(tree: Tree, pos_tree: np.ndarray, theta: float, eps: float,
+                    n_images: Optional[int] = None) -> FmmLists:
+    """The sink-cell walk with CC and CP interactions (Sec. 3.1)."""
+    L = tree.box_L
+    if n_images is None:
+        n_images = 27 if L > 0 else 1
+    pos_tree = np.ascontiguousarray(pos_tree, dtype=np.float64)
+    nb, nc = tree.n_bucket, tree.n_cell
+    pp_off = np.zeros(nb + 1, np.int64)
+    pc_off = np.zeros(nb + 1, np.int64)
+    cc_off = np.zeros(nc + 1, np.int64)
+    head = (nc, _p(tree.cell_first), _p(tree.cell_count), _p(tree.child), _p(tree.com),
+            _p(tree.bmax), _p(tree.bbox), _p(pos_tree), float(theta), float(eps), float(L),
+            int(n_images))
+    lib().orc_fmm_walk(*head, 0, _p(pp_off), None, None, None, _p(pc_off), None, None,
+                       _p(cc_off), None, None)
+    out = dict(pp_src=np.empty(pp_off[-1], np.int32), pp_img=np.empty(pp_off[-1], np.uint8),
+               pp_sub=np.empty(pp_off[-1], np.uint8), pc_src=np.empty(pc_off[-1], np.int32),
+               pc_img=np.empty(pc_off[-1], np.uint8), cc_src=np.empty(cc_off[-1], np.int32),
+               cc_img=np.empty(cc_off[-1], np.uint8))
+    lib().orc_fmm_walk(*head, 1, _p(pp_off), _p(out["pp_src"]), _p(out["pp_img"]),
+                       _p(out["pp_sub"]), _p(pc_off), _p(out["pc_src"]), _p(out["pc_img"]),
+                       _p(cc_off), _p(out["cc_src"]), _p(out["cc_img"]))
+    return FmmLists(pp_off, out["pp_src"], out["pp_img"], out["pp_sub"], pc_off, out["pc_src"],
+                    out["pc_img"], cc_off, out["cc_src"], out["cc_img"], int(n_images))
+
+
+def fmm_local(tree: Tree, fl: FmmLists, pos_tree: np.ndarray, mass_tree: np.ndarray,
+              eps: float) -> np.ndarray:
+    """Local expansion of every cell: [n_cell, 364], the full tensors of
+    orders 0..5 of d^a phi at the cell's centre of mass."""
+    pos_tree = np.ascontiguousarray(pos_tree, dtype=np.float64)
+    mass_tree = np.ascontiguousarray(mass_tree, dtype=np.float64)
+    out = np.empty((tree.n_cell, 364))
+    lib().orc_fmm_local(tree.n_cell, _p(tree.child), _p(tree.com), _p(tree.mom), _p(pos_tree),
+                        _p(mass_tree), float(eps), float(tree.box_L), _p(fl.cc_off),
+                        _p(fl.cc_src), _p(fl.cc_img), _p(out))
+    return out
+
+
+def fmm_evaluate(tree: Tree, fl: FmmLists, pos_tree: np.ndarray, mass_tree: np.ndarray,
+                 eps: float, parts: int = 7, local: Optional[np.ndarray] = None,
+                 ewald: Optional[dict] = None):
+    """Accelerations and potentials (tree order) from the FMM lists: PP and
+    PC of each bucket (bits 1, 2), the Ewald correction (bit 4) and, with
+    bit 8, the buckets' local expansions evaluated at their particles."""
+    ew = dict(EXACT_EWALD if ewald is None else ewald)
+    pos_tree = np.ascontiguousarray(pos_tree, dtype=np.float64)
+    mass_tree = np.ascontiguousarray(mass_tree, dtype=np.float64)
+    n = pos_tree.shape[0]
+    acc = np.zeros((n, 3))
+    pot = np.zeros(n)
+    if parts & 7:
+        lib().orc_eval_sub(n, _p(pos_tree), _p(mass_tree), float(eps), float(tree.box_L),
+                           _p(tree.cell_first), _p(tree.cell_count), _p(tree.com), _p(tree.mom),
+                           tree.n_bucket, _p(tree.bucket_cell), _p(fl.pp_off), _p(fl.pp_src),
+                           _p(fl.pp_img), _p(fl.pp_sub), _p(fl.pc_off), _p(fl.pc_src),
+                           _p(fl.pc_img), 0, None, int(parts & 7), float(ew["alpha"]),
+                           int(ew["rmax"]), int(ew["h2max"]), _p(acc), _p(pot))
+    if parts & 8:
+        if local is None:
+            local = fmm_local(tree, fl, pos_tree, mass_tree, eps)
+        a2, p2 = np.zeros((n, 3)), np.zeros(n)
+        lib().orc_fmm_l2p(tree.n_bucket, _p(tree.bucket_cell), _p(tree.cell_first),
+                          _p(tree.cell_count), _p(tree.com), _p(pos_tree),
+                          _p(np.ascontiguousarray(local)), _p(a2), _p(p2))
+        acc += a2
+        pot += p2
+    return acc, pot
+
+
+def fmm_m2l_point(mom32, mass: float, part: bool, XS, XC, eps: float) -> np.ndarray:
+    out = np.empty(364)
+    m = np.ascontiguousarray(mom32 if mom32 is not None else np.zeros(32), dtype=np.float64)
+    lib().orc_fmm_m2l_point(_p(m), float(mass), int(part), _p(np.asarray(XS, np.float64)),
+                            _p(np.asarray(XC, np.float64)), float(eps), _p(out))
+    return out
+
+
+def fmm_l2l_point(L364, d) -> np.ndarray:
+    out = np.empty(364)
+    lib().orc_fmm_l2l_point(_p(np.ascontiguousarray(L364, np.float64)),
+                            _p(np.asarray(d, np.float64)), _p(out))
+    return out
+
+
+def fmm_l2p_point(L364, h) -> np.ndarray:
+    out = np.empty(4)
+    lib().orc_fmm_l2p_point(_p(np.ascontiguousarray(L364, np.float64)),
+                            _p(np.asarray(h, np.float64)), _p(out))
+    return out
 
 
 def direct_open(pos: np.ndarray, mass: np.ndarray, eps: float):

@@ -874,6 +874,14 @@ void orc_ewald_root_point(const double *mom32, const double X[3], const double x
 /* parts: bit 0 = PP, bit 1 = PC, bit 2 = Ewald.  Self term (i, image 0) */
 /* is excluded from PP; the particle's own replicas are included.       */
 /* ------------------------------------------------------------------ */
+void orc_eval_sub(int64_t n, const double *pos, const double *mass, double eps, double L,
+                  const int64_t *cell_first, const int32_t *cell_count, const double *com,
+                  const double *mom, int64_t n_bucket, const int32_t *bucket_cell,
+                  const int64_t *pp_off, const int32_t *pp_src, const uint8_t *pp_img,
+                  const uint8_t *pp_sub, const int64_t *pc_off, const int32_t *pc_src,
+                  const uint8_t *pc_img, int64_t n_sel, const int32_t *sel, int parts,
+                  double ew_alpha, int ew_rmax, int ew_h2max, double *acc, double *pot);
+
 void orc_eval(int64_t n, const double *pos, const double *mass, double eps, double L,
               const int64_t *cell_first, const int32_t *cell_count, const double *com,
               const double *mom, int64_t n_bucket, const int32_t *bucket_cell,
@@ -881,6 +889,21 @@ void orc_eval(int64_t n, const double *pos, const double *mass, double eps, doub
               const int64_t *pc_off, const int32_t *pc_src, const uint8_t *pc_img,
               int64_t n_sel, const int32_t *sel, int parts, double ew_alpha, int ew_rmax,
               int ew_h2max, double *acc, double *pot) {
+    orc_eval_sub(n, pos, mass, eps, L, cell_first, cell_count, com, mom, n_bucket, bucket_cell,
+                 pp_off, pp_src, pp_img, NULL, pc_off, pc_src, pc_img, n_sel, sel, parts,
+                 ew_alpha, ew_rmax, ew_h2max, acc, pot);
+}
+
+/* As orc_eval, with PP entries that may name a single particle of their
+ * source leaf: pp_sub[e] = 0 for the whole leaf, k + 1 for its k-th
+ * particle (pp_sub NULL: whole leaves). */
+void orc_eval_sub(int64_t n, const double *pos, const double *mass, double eps, double L,
+                  const int64_t *cell_first, const int32_t *cell_count, const double *com,
+                  const double *mom, int64_t n_bucket, const int32_t *bucket_cell,
+                  const int64_t *pp_off, const int32_t *pp_src, const uint8_t *pp_img,
+                  const uint8_t *pp_sub, const int64_t *pc_off, const int32_t *pc_src,
+                  const uint8_t *pc_img, int64_t n_sel, const int32_t *sel, int parts,
+                  double ew_alpha, int ew_rmax, int ew_h2max, double *acc, double *pot) {
     orc_init();
     if (gl_n == 0) orc_set_quadrature(128);
     (void)n;
@@ -898,7 +921,12 @@ void orc_eval(int64_t n, const double *pos, const double *mass, double eps, doub
                     int64_t c = pp_src[e];
                     double sh[3];
                     orc_image_shift(pp_img[e], L, sh);
-                    for (int64_t j = cell_first[c]; j < cell_first[c] + cell_count[c]; ++j) {
+                    int64_t j0 = cell_first[c], j1 = cell_first[c] + cell_count[c];
+                    if (pp_sub && pp_sub[e] > 0) {
+                        j0 = cell_first[c] + pp_sub[e] - 1;
+                        j1 = j0 + 1;
+                    }
+                    for (int64_t j = j0; j < j1; ++j) {
                         if (j == i && pp_img[e] == 0) continue;
                         double rx = x[0] - (pos[3 * j] + sh[0]);
                         double ry = x[1] - (pos[3 * j + 1] + sh[1]);
@@ -1008,4 +1036,402 @@ void orc_direct_periodic(int64_t n, const double *pos, const double *mass, doubl
         acc[3 * i + 2] = az;
         pot[i] = ph;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Fast multipole form of the walk (Sec. 3.1): cell-cell (CC) and      */
+/* cell-particle (CP) interactions into a local expansion of the       */
+/* potential about each sink cell's centre of mass, to 5th order.      */
+/*                                                                    */
+/* Sink cells are visited in node-left-right order from the root, the  */
+/* root's checklist holding the root seen through every image.  A sink */
+/* S takes its checklist from the front (opened cells append their     */
+/* children at the end).  A source C (a cell, or a particle of an      */
+/* opened leaf: RO = 0, b_max = 0, a point box) seen through image n   */
+/* is                                                                  */
+/*   CC (cell) or CP (particle) if |X_C + nL - X_S| > 1.5 RO_S + RO_C    */
+/*       and the boxes are at least 2 eps apart (the sink's opening     */
+/*       radius enlarged by the paper's factor 1.5),                    */
+/*   at a leaf S (a bucket: the group is the bucket):                   */
+/*     PP of the single particle for a particle source,                */
+/*     PC if |X_C + nL - X_S| > RO_C + b_max,S and the boxes are at     */
+/*         least 2 eps apart (the rule of the bucket walk),             */
+/*     PP of the whole bucket C if C is a leaf, else opened;            */
+/*   at a larger S: a particle source is kept for the sink's children; */
+/*     a cell source at least as large as the sink (b_max,C >= b_max,S) */
+/*     is opened (a leaf into its particles, in order), a smaller one   */
+/*     kept.                                                            */
+/* Children of S start from the kept entries, in order.                */
+/*                                                                    */
+/* The local expansion of S holds L_a = d^a phi(X_S) for |a| <= 5:      */
+/*   CC: L_a = sum_{k in {0,2,3,4}, k + |a| <= 5} (-1)^k/k! M_k .       */
+/*             d^(k+a) G(R),  R = X_S - X_C - nL                        */
+/*   CP: L_a = m d^a G(R),  R = X_S - x_p - nL                          */
+/* (terms of total order above 5 are dropped); a child's expansion is   */
+/* its own plus its parent's shifted to it,                            */
+/*   L'_a = sum_{b >= a} L_b d^(b-a)/(b-a)!,  d = X_child - X_parent,   */
+/* and a particle at x in a bucket S gets                              */
+/*   phi = sum_a L_a h^a/a!,  acc = -grad phi,  h = x - X_S.            */
+/* All tensors are full Cartesian tensors (3^n components of order n).  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t idx;  /* cell, or tree-order particle */
+    int img;
+    int part;     /* 1: a particle (of leaf `leaf`, index `sub` in it) */
+    int64_t leaf;
+    int sub;
+} FEnt;
+
+typedef struct {
+    FEnt *e;
+    int64_t n, cap;
+} FList;
+
+static void fl_push(FList *l, FEnt x) {
+    if (l->n == l->cap) {
+        l->cap = l->cap ? 2 * l->cap : 256;
+        l->e = (FEnt *)realloc(l->e, sizeof(FEnt) * (size_t)l->cap);
+    }
+    l->e[l->n++] = x;
+}
+
+typedef struct {
+    const int64_t *cell_first;
+    const int32_t *cell_count;
+    const int32_t *child;
+    const double *com, *bmax, *bbox, *pos;
+    double theta, eps, L;
+    int fill;
+    /* bucket lists (per leaf, in leaf order) and cell lists */
+    int64_t bucket, *pp_off, *pc_off, *cc_off;
+    int32_t *pp_src, *pc_src, *cc_src;
+    uint8_t *pp_img, *pp_sub, *pc_img, *cc_img;
+    int64_t npp, npc, ncc;
+} FWalk;
+
+static void fmm_source(const FWalk *w, const FEnt *e, double X[3], double lo[3], double hi[3],
+                       double *ro, double *bm) {
+    double sh[3];
+    orc_image_shift(e->img, w->L, sh);
+    if (e->part) {
+        for (int d = 0; d < 3; ++d) {
+            X[d] = w->pos[3 * e->idx + d] + sh[d];
+            lo[d] = hi[d] = X[d];
+        }
+        *ro = 0.0;
+        *bm = 0.0;
+    } else {
+        for (int d = 0; d < 3; ++d) {
+            X[d] = w->com[3 * e->idx + d] + sh[d];
+            lo[d] = w->bbox[6 * e->idx + d] + sh[d];
+            hi[d] = w->bbox[6 * e->idx + 3 + d] + sh[d];
+        }
+        *ro = w->bmax[e->idx] / w->theta;
+        *bm = w->bmax[e->idx];
+    }
+}
+
+static double box_gap(const double lo[3], const double hi[3], const double *sb) {
+    double g2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double g = 0.0;
+        if (lo[a] - sb[3 + a] > g) g = lo[a] - sb[3 + a];
+        if (sb[a] - hi[a] > g) g = sb[a] - hi[a];
+        g2 += g * g;
+    }
+    return sqrt(g2);
+}
+
+static void fmm_sink(FWalk *w, int64_t S, const FList *in) {
+    FList q = {0, 0, 0}, keep = {0, 0, 0};
+    for (int64_t i = 0; i < in->n; ++i) fl_push(&q, in->e[i]);
+    const int leaf = w->child[2 * S] < 0;
+    const double *XS = w->com + 3 * S, *sb = w->bbox + 6 * S;
+    const double ro_s = w->bmax[S] / w->theta;
+    int64_t b = -1;
+    if (leaf) {
+        b = w->bucket++;
+        if (!w->fill) {
+            w->pp_off[b + 1] = 0;
+            w->pc_off[b + 1] = 0;
+        }
+    }
+    int64_t kpp = 0, kpc = 0, kcc = 0;
+    for (int64_t i = 0; i < q.n; ++i) {
+        FEnt e = q.e[i];
+        double X[3], lo[3], hi[3], ro, bm;
+        fmm_source(w, &e, X, lo, hi, &ro, &bm);
+        double dx = X[0] - XS[0], dy = X[1] - XS[1], dz = X[2] - XS[2];
+        double d = sqrt(dx * dx + dy * dy + dz * dz);
+        double gap = box_gap(lo, hi, sb);
+        if (d > 1.5 * ro_s + ro && gap >= 2.0 * w->eps) {
+            if (w->fill) {
+                int64_t k = w->cc_off[S] + kcc;
+                w->cc_src[k] = e.part ? (int32_t)~e.idx : (int32_t)e.idx;
+                w->cc_img[k] = (uint8_t)e.img;
+            }
+            ++kcc;
+        } else if (leaf) {
+            if (e.part) {
+                if (w->fill) {
+                    int64_t k = w->pp_off[b] + kpp;
+                    w->pp_src[k] = (int32_t)e.leaf;
+                    w->pp_img[k] = (uint8_t)e.img;
+                    w->pp_sub[k] = (uint8_t)(e.sub + 1);
+                }
+                ++kpp;
+            } else if (d > ro + w->bmax[S] && gap >= 2.0 * w->eps) {
+                if (w->fill) {
+                    int64_t k = w->pc_off[b] + kpc;
+                    w->pc_src[k] = (int32_t)e.idx;
+                    w->pc_img[k] = (uint8_t)e.img;
+                }
+                ++kpc;
+            } else if (w->child[2 * e.idx] < 0) {
+                if (w->fill) {
+                    int64_t k = w->pp_off[b] + kpp;
+                    w->pp_src[k] = (int32_t)e.idx;
+                    w->pp_img[k] = (uint8_t)e.img;
+                    w->pp_sub[k] = 0;
+                }
+                ++kpp;
+            } else {
+                for (int s = 0; s < 2; ++s) {
+                    FEnt c = {w->child[2 * e.idx + s], e.img, 0, -1, 0};
+                    fl_push(&q, c);
+                }
+            }
+        } else if (e.part) {
+            fl_push(&keep, e);
+        } else if (bm >= w->bmax[S]) {
+            if (w->child[2 * e.idx] < 0) {
+                for (int s = 0; s < w->cell_count[e.idx]; ++s) {
+                    FEnt p = {w->cell_first[e.idx] + s, e.img, 1, e.idx, s};
+                    fl_push(&q, p);
+                }
+            } else {
+                for (int s = 0; s < 2; ++s) {
+                    FEnt c = {w->child[2 * e.idx + s], e.img, 0, -1, 0};
+                    fl_push(&q, c);
+                }
+            }
+        } else {
+            fl_push(&keep, e);
+        }
+    }
+    free(q.e);
+    if (!w->fill) {
+        w->cc_off[S + 1] = kcc;
+        if (leaf) {
+            w->pp_off[b + 1] = kpp;
+            w->pc_off[b + 1] = kpc;
+        }
+    }
+    if (!leaf) {
+        fmm_sink(w, w->child[2 * S], &keep);
+        fmm_sink(w, w->child[2 * S + 1], &keep);
+    }
+    free(keep.e);
+}
+
+/* Two passes, as the bucket walk: fill = 0 writes per-bucket PP / PC
+ * lengths into pp_off[1..], pc_off[1..] and per-cell CC/CP lengths into
+ * cc_off[1..], then turns them into offsets; fill = 1 writes the entries
+ * (PP: source leaf, image, sub = 0 for the whole leaf or k + 1 for its
+ * k-th particle; CC/CP: source cell, or ~p for tree-order particle p). */
+void orc_fmm_walk(int64_t n_cell, const int64_t *cell_first, const int32_t *cell_count,
+                  const int32_t *child, const double *com, const double *bmax, const double *bbox,
+                  const double *pos, double theta, double eps, double L, int n_img, int fill,
+                  int64_t *pp_off, int32_t *pp_src, uint8_t *pp_img, uint8_t *pp_sub,
+                  int64_t *pc_off, int32_t *pc_src, uint8_t *pc_img, int64_t *cc_off,
+                  int32_t *cc_src, uint8_t *cc_img) {
+    FWalk w = {cell_first, cell_count, child, com, bmax, bbox, pos, theta, eps, L, fill, 0,
+               pp_off, pc_off, cc_off, pp_src, pc_src, cc_src, pp_img, pp_sub, pc_img, cc_img,
+               0, 0, 0};
+    FList root = {0, 0, 0};
+    for (int i = 0; i < n_img; ++i) {
+        FEnt e = {0, i, 0, -1, 0};
+        fl_push(&root, e);
+    }
+    if (!fill) {
+        pp_off[0] = pc_off[0] = cc_off[0] = 0;
+    }
+    fmm_sink(&w, 0, &root);
+    free(root.e);
+    if (!fill) {
+        for (int64_t b = 0; b < w.bucket; ++b) {
+            pp_off[b + 1] += pp_off[b];
+            pc_off[b + 1] += pc_off[b];
+        }
+        for (int64_t c = 0; c < n_cell; ++c) cc_off[c + 1] += cc_off[c];
+    }
+}
+
+#define FMM_P 5
+/* offsets of the order-n blocks in a 364-value full local expansion */
+static const int LOFF[FMM_P + 2] = {0, 1, 4, 13, 40, 121, 364};
+
+/* Derivative tensors of G = -g through order 5 at R. */
+static void green_tensors(const double R[3], double eps2, double *T[]) {
+    double a[ORC_KMAX + 1];
+    plummer_radial(R[0] * R[0] + R[1] * R[1] + R[2] * R[2], eps2, FMM_P, a);
+    radial_tensors(R, a, FMM_P, T);
+    for (int n = 0; n <= FMM_P; ++n)
+        for (int f = 0; f < POW3[n]; ++f) T[n][f] = -T[n][f];
+}
+
+/* Add the CC or CP contribution of one entry to the expansion Lc (364). */
+static void fmm_m2l(const double *mom, double mass, int part, const double XS[3],
+                    const double XC[3], double eps2, double *Lc) {
+    static const double fact[6] = {1, 1, 2, 6, 24, 120};
+    double R[3] = {XS[0] - XC[0], XS[1] - XC[1], XS[2] - XC[2]};
+    double T0[1], T1[3], T2[9], T3[27], T4[81], T5[243];
+    double *T[6] = {T0, T1, T2, T3, T4, T5};
+    green_tensors(R, eps2, T);
+    if (part) {
+        for (int n = 0; n <= FMM_P; ++n)
+            for (int f = 0; f < POW3[n]; ++f) Lc[LOFF[n] + f] += mass * T[n][f];
+        return;
+    }
+    double M2[9], M3[27], M4[81];
+    unpack_moments(mom, M2, M3, M4);
+    double M0[1] = {mom[0]};
+    const double *Mk[5] = {M0, NULL, M2, M3, M4};
+    for (int n = 0; n <= FMM_P; ++n)
+        for (int k = 0; k <= 4 && k + n <= FMM_P; ++k) {
+            if (k == 1) continue;
+            double c = ((k & 1) ? -1.0 : 1.0) / fact[k];
+            for (int f = 0; f < POW3[n]; ++f) {
+                double s = 0.0;
+                for (int j = 0; j < POW3[k]; ++j) s += Mk[k][j] * T[k + n][j * POW3[n] + f];
+                Lc[LOFF[n] + f] += c * s;
+            }
+        }
+}
+
+/* L' = L shifted from its centre by d (both 364 values). */
+static void fmm_l2l(const double *L, const double d[3], double *out) {
+    static const double fact[6] = {1, 1, 2, 6, 24, 120};
+    for (int n = 0; n <= FMM_P; ++n)
+        for (int f = 0; f < POW3[n]; ++f) {
+            double s = 0.0;
+            for (int m = n; m <= FMM_P; ++m) {
+                int k = m - n;
+                for (int j = 0; j < POW3[k]; ++j) {
+                    int ax[ORC_KMAX];
+                    digits(k, j, ax);
+                    double dp = 1.0;
+                    for (int q = 0; q < k; ++q) dp *= d[ax[q]];
+                    s += L[LOFF[m] + f * POW3[k] + j] * dp / fact[k];
+                }
+            }
+            out[LOFF[n] + f] = s;
+        }
+}
+
+/* Potential and acceleration at offset h from the expansion's centre. */
+static void fmm_l2p(const double *L, const double h[3], double out[4]) {
+    static const double fact[6] = {1, 1, 2, 6, 24, 120};
+    double phi = 0.0, g[3] = {0, 0, 0};
+    for (int n = 0; n <= FMM_P; ++n)
+        for (int f = 0; f < POW3[n]; ++f) {
+            int ax[ORC_KMAX];
+            digits(n, f, ax);
+            double hp = 1.0;
+            for (int q = 0; q < n; ++q) hp *= h[ax[q]];
+            phi += L[LOFF[n] + f] * hp / fact[n];
+            if (n >= 1) {
+                /* d/dh_a of the order-n term: the first index is a, the
+                 * rest contracted with h (symmetric tensor) */
+                double hq = 1.0;
+                for (int q = 1; q < n; ++q) hq *= h[ax[q]];
+                g[ax[0]] += L[LOFF[n] + f] * hq / fact[n - 1];
+            }
+        }
+    out[0] = -g[0];
+    out[1] = -g[1];
+    out[2] = -g[2];
+    out[3] = phi;
+}
+
+/* Local expansions of every cell (364 values each, about its centre of
+ * mass): own CC/CP contributions, then shifted down from the root in
+ * node-left-right order (parents come before their children). */
+void orc_fmm_local(int64_t n_cell, const int32_t *child, const double *com, const double *mom,
+                   const double *pos, const double *mass, double eps, double L,
+                   const int64_t *cc_off, const int32_t *cc_src, const uint8_t *cc_img,
+                   double *local) {
+    orc_init();
+    double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < n_cell; ++c) {
+        double *Lc = local + 364 * c;
+        for (int f = 0; f < 364; ++f) Lc[f] = 0.0;
+        for (int64_t e = cc_off[c]; e < cc_off[c + 1]; ++e) {
+            double sh[3], X[3];
+            orc_image_shift(cc_img[e], L, sh);
+            int32_t s = cc_src[e];
+            if (s < 0) {
+                int64_t p = ~(int64_t)s;
+                for (int d = 0; d < 3; ++d) X[d] = pos[3 * p + d] + sh[d];
+                fmm_m2l(NULL, mass[p], 1, com + 3 * c, X, eps2, Lc);
+            } else {
+                for (int d = 0; d < 3; ++d) X[d] = com[3 * s + d] + sh[d];
+                fmm_m2l(mom + 32 * s, 0.0, 0, com + 3 * c, X, eps2, Lc);
+            }
+        }
+    }
+    double *tmp = (double *)malloc(sizeof(double) * 364);
+    for (int64_t p = 0; p < n_cell; ++p) {
+        if (child[2 * p] < 0) continue;
+        for (int s = 0; s < 2; ++s) {
+            int64_t c = child[2 * p + s];
+            double d[3] = {com[3 * c] - com[3 * p], com[3 * c + 1] - com[3 * p + 1],
+                           com[3 * c + 2] - com[3 * p + 2]};
+            fmm_l2l(local + 364 * p, d, tmp);
+            for (int f = 0; f < 364; ++f) local[364 * c + f] += tmp[f];
+        }
+    }
+    free(tmp);
+}
+
+/* The local expansion of each particle's bucket evaluated at it (L2P),
+ * written to acc / pot of the particles of the selected buckets. */
+void orc_fmm_l2p(int64_t n_bucket, const int32_t *bucket_cell, const int64_t *cell_first,
+                 const int32_t *cell_count, const double *com, const double *pos,
+                 const double *local, double *acc, double *pot) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < n_bucket; ++b) {
+        int64_t c = bucket_cell[b];
+        for (int64_t i = cell_first[c]; i < cell_first[c] + cell_count[c]; ++i) {
+            double h[3] = {pos[3 * i] - com[3 * c], pos[3 * i + 1] - com[3 * c + 1],
+                           pos[3 * i + 2] - com[3 * c + 2]};
+            double o[4];
+            fmm_l2p(local + 364 * c, h, o);
+            acc[3 * i] = o[0];
+            acc[3 * i + 1] = o[1];
+            acc[3 * i + 2] = o[2];
+            pot[i] = o[3];
+        }
+    }
+}
+
+/* The exposed parts of the expansion machinery, for the pins: the
+ * expansion of one source (cell moments or a particle) about X_S, its
+ * shift, and its evaluation. */
+void orc_fmm_m2l_point(const double *mom32, double mass, int part, const double XS[3],
+                       const double XC[3], double eps, double *L364) {
+    orc_init();
+    for (int f = 0; f < 364; ++f) L364[f] = 0.0;
+    fmm_m2l(mom32, mass, part, XS, XC, eps * eps, L364);
+}
+
+void orc_fmm_l2l_point(const double *L364, const double d[3], double *out364) {
+    orc_init();
+    fmm_l2l(L364, d, out364);
+}
+
+void orc_fmm_l2p_point(const double *L364, const double h[3], double out[4]) {
+    orc_init();
+    fmm_l2p(L364, h, out);
 }
