@@ -301,6 +301,83 @@ mgrav_status mgrav_store_active(mgrav_ctx *ctx, int64_t n, const mgrav_store *st
                                 uint8_t *active);
 
 /* ------------------------------------------------------------------ */
+/* Fast multipole form (Sec. 3.1): cell-cell (CC) and cell-particle    */
+/* (CP) interactions into local expansions of each sink cell.          */
+/* ------------------------------------------------------------------ */
+
+/* The walk over sink cells, in node-left-right order from the root
+ * (checklist: the root through every image), each with the checklist its
+ * parent kept.  A source -- a cell, or a particle of an opened leaf
+ * (opening radius 0, a point box) -- seen through image n is, for sink S:
+ *   CC (cell) / CP (particle) if |X_C + nL - X_S| > 1.5 RO_S + RO_C and
+ *     the boxes are at least 2 eps apart (RO = b_max / theta; the factor
+ *     1.5 on the sink is the paper's);
+ *   at a bucket S: PP of the particle for a particle source; PC if
+ *     |X_C + nL - X_S| > RO_C + b_max,S with the boxes 2 eps apart (the
+ *     bucket walk's rule); PP of the whole leaf if C is a leaf; else
+ *     opened (children appended to the checklist);
+ *   at a larger S: a particle, or a cell smaller than S (b_max,C <
+ *     b_max,S), stays on the checklist of S's children; a cell at least as
+ *     large is opened (a leaf into its particles, in tree order).
+ * Outputs (host, like mgrav_lists_*_host): per bucket pp_off / pc_off
+ * [n_bucket + 1] and entries pp_src, pp_img, pp_sub (0: the whole leaf,
+ * k + 1: its k-th particle), pc_src, pc_img; per cell cc_off [n_cell + 1]
+ * and entries cc_src (source cell, or ~p for tree-order particle p),
+ * cc_img.  pos: tree-order positions [n][3] (host). */
+mgrav_status mgrav_fmm_lists_count_host(int64_t n_cell, const int64_t *cell_first,
+                                        const int32_t *cell_count, const int32_t *child,
+                                        const double *com, const double *bmax,
+                                        const double *bbox, const double *pos, double theta,
+                                        double eps, double L, int n_images, int64_t *pp_off,
+                                        int64_t *pc_off, int64_t *cc_off);
+mgrav_status mgrav_fmm_lists_fill_host(int64_t n_cell, const int64_t *cell_first,
+                                       const int32_t *cell_count, const int32_t *child,
+                                       const double *com, const double *bmax, const double *bbox,
+                                       const double *pos, double theta, double eps, double L,
+                                       int n_images, const int64_t *pp_off, const int64_t *pc_off,
+                                       const int64_t *cc_off, int32_t *pp_src, uint8_t *pp_img,
+                                       uint8_t *pp_sub, int32_t *pc_src, uint8_t *pc_img,
+                                       int32_t *cc_src, uint8_t *cc_img);
+
+/* The CC / CP part of the forces, on the device (all pointers device
+ * memory; particles and cells as for mgrav_bind). */
+typedef struct {
+    int64_t n, n_cell, n_bucket;
+    const int32_t *child;
+    const double *com;
+    const double *mom;
+    const int64_t *cell_first;
+    const int32_t *cell_count;
+    const int32_t *bucket_cell;
+    const double *pos;        /* [n][3] tree order */
+    const double *mass;       /* [n], or NULL: mass_uniform */
+    double mass_uniform;
+    double eps, box_L;
+    const int64_t *cc_off;    /* [n_cell + 1] */
+    const int32_t *cc_src;
+    const uint8_t *cc_img;
+    const uint8_t *active;    /* [n] or NULL: every particle */
+} mgrav_fmm;
+
+/* Device workspace of mgrav_fmm_apply (56 doubles and 4 bytes per cell). */
+mgrav_status mgrav_fmm_workspace_size(int64_t n_cell, size_t *bytes);
+
+/* Every cell's own local expansion L_a = d^a phi(X_S), |a| <= 5 (56
+ * values, about its centre of mass), from its CC entries,
+ *   L_a = sum_{k in {0,2,3,4}, k + |a| <= 5} (-1)^k/k! M_k . d^(k+a) G(R),
+ * and CP entries, L_a = m d^a G(R) (R = X_S - source - nL, G = -(R^2 +
+ * eps^2)^(-1/2), total order kept to 5); each bucket's expansion is its
+ * ancestors' shifted down one level at a time (L'_a = sum_{b >= a} L_b
+ * d^(b-a)/(b-a)!) plus its own, and is evaluated at its active particles:
+ * acc -= grad phi, pot += phi (phi = sum_a L_a h^a/a!), added in double
+ * and rounded once.  Call after mgrav_compute on the same stream (acc, pot
+ * as it writes them).  Double precision.  local_out (nullable, device
+ * [n_bucket][56]) receives the buckets' expansions.  Blocking.  BAD_LIST
+ * for an entry out of range; INVALID_ARG / NO_MEMORY as usual. */
+mgrav_status mgrav_fmm_apply(mgrav_ctx *ctx, const mgrav_fmm *f, void *workspace, size_t bytes,
+                             float *acc, float *pot, double *local_out);
+
+/* ------------------------------------------------------------------ */
 /* Device-side evaluation.                                             */
 /* ------------------------------------------------------------------ */
 
@@ -340,6 +417,10 @@ typedef struct {
     double q_scale;
     /* With mass == NULL every particle has this mass (> 0). */
     double mass_uniform;
+    /* PP entries naming one particle of their source leaf (nullable: whole
+     * leaves): pp_sub[e] = 0 for the whole leaf pp_src[e], k + 1 for its
+     * k-th particle in tree order (the walk of mgrav_fmm_lists_*_host). */
+    const uint8_t *pp_sub;
 } mgrav_problem;
 
 /* Device workspace the caller must provide to mgrav_bind for `p`:

@@ -54,6 +54,7 @@ class Problem(ctypes.Structure):
         ("bucket_cell", _P), ("pp_off", _P), ("pp_src", _P), ("pp_img", _P), ("pc_off", _P),
         ("pc_src", _P), ("pc_img", _P), ("n_pp", _I64), ("n_pc", _I64),
         ("pos_q", _P), ("q_origin", _D * 3), ("q_scale", _D), ("mass_uniform", _D),
+        ("pp_sub", _P),
     ]
 
 
@@ -87,6 +88,13 @@ class Walk(ctypes.Structure):
     _fields_ = [("n_cell", _I64), ("child", _P), ("com", _P), ("bmax", _P), ("bbox", _P),
                 ("n_roots", _I), ("roots", ctypes.c_int32 * 2), ("theta", _D), ("eps", _D),
                 ("L", _D), ("n_images", _I), ("n_sink", _I64), ("sink_cell", _P)]
+
+
+class Fmm(ctypes.Structure):
+    _fields_ = [("n", _I64), ("n_cell", _I64), ("n_bucket", _I64), ("child", _P), ("com", _P),
+                ("mom", _P), ("cell_first", _P), ("cell_count", _P), ("bucket_cell", _P),
+                ("pos", _P), ("mass", _P), ("mass_uniform", _D), ("eps", _D), ("box_L", _D),
+                ("cc_off", _P), ("cc_src", _P), ("cc_img", _P), ("active", _P)]
 
 
 class TrainConfig(ctypes.Structure):
@@ -193,6 +201,16 @@ def _declare():
     L.mgrav_store_rungs.argtypes = [_P, _I64, SP, _P, _D, _D, _D, _I, _I, _I]
     L.mgrav_store_active.restype = _I
     L.mgrav_store_active.argtypes = [_P, _I64, SP, _I, _P]
+    L.mgrav_fmm_lists_count_host.restype = _I
+    L.mgrav_fmm_lists_count_host.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _I,
+                                             _P, _P, _P]
+    L.mgrav_fmm_lists_fill_host.restype = _I
+    L.mgrav_fmm_lists_fill_host.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _I,
+                                            _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.mgrav_fmm_workspace_size.restype = _I
+    L.mgrav_fmm_workspace_size.argtypes = [_I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgrav_fmm_apply.restype = _I
+    L.mgrav_fmm_apply.argtypes = [_P, ctypes.POINTER(Fmm), _P, ctypes.c_size_t, _P, _P, _P]
     L.mgrav_watchdog_poll.restype = _I
     L.mgrav_watchdog_poll.argtypes = [WATCHDOG_QUERY, _P, _D]
 
@@ -212,7 +230,8 @@ EXPORTS = (
     "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_lists_workspace_size",
     "mgrav_lists_count", "mgrav_lists_fill", "mgrav_store_encode", "mgrav_store_decode",
     "mgrav_store_permute", "mgrav_store_drift", "mgrav_store_kick", "mgrav_store_rungs",
-    "mgrav_store_active",
+    "mgrav_store_active", "mgrav_fmm_lists_count_host", "mgrav_fmm_lists_fill_host",
+    "mgrav_fmm_workspace_size", "mgrav_fmm_apply",
 )
 
 
@@ -420,6 +439,54 @@ def lists_build(tree: Tree, theta: float, eps: float, n_images: Optional[int] = 
                  int(n_images))
 
 
+@dataclasses.dataclass
+class FmmLists:
+    """Lists of the fast-multipole walk (include/mgrav.h): per bucket PP
+    (with pp_sub) and PC entries, per cell CC / CP entries."""
+    pp_off: np.ndarray
+    pp_src: np.ndarray
+    pp_img: np.ndarray
+    pp_sub: np.ndarray
+    pc_off: np.ndarray
+    pc_src: np.ndarray
+    pc_img: np.ndarray
+    cc_off: np.ndarray
+    cc_src: np.ndarray
+    cc_img: np.ndarray
+    n_images: int
+
+
+def fmm_lists_build(tree: Tree, pos_tree: np.ndarray, theta: float, eps: float,
+                    n_images: Optional[int] = None) -> FmmLists:
+    """The fast-multipole walk on the host (C++/OpenMP)."""
+    if n_images is None:
+        n_images = 27 if tree.box_L > 0 else 1
+    pos_tree = np.ascontiguousarray(pos_tree, dtype=np.float64)
+    nb, nc = tree.n_bucket, tree.n_cell
+    pp_off = np.zeros(nb + 1, np.int64)
+    pc_off = np.zeros(nb + 1, np.int64)
+    cc_off = np.zeros(nc + 1, np.int64)
+    head = (nc, _ptr(tree.cell_first), _ptr(tree.cell_count), _ptr(tree.child), _ptr(tree.com),
+            _ptr(tree.bmax), _ptr(tree.bbox), _ptr(pos_tree), float(theta), float(eps),
+            float(tree.box_L), int(n_images))
+    _check(_lib.mgrav_fmm_lists_count_host(*head, _ptr(pp_off), _ptr(pc_off), _ptr(cc_off)))
+    o = dict(pp_src=np.empty(max(1, pp_off[-1]), np.int32),
+             pp_img=np.empty(max(1, pp_off[-1]), np.uint8),
+             pp_sub=np.empty(max(1, pp_off[-1]), np.uint8),
+             pc_src=np.empty(max(1, pc_off[-1]), np.int32),
+             pc_img=np.empty(max(1, pc_off[-1]), np.uint8),
+             cc_src=np.empty(max(1, cc_off[-1]), np.int32),
+             cc_img=np.empty(max(1, cc_off[-1]), np.uint8))
+    _check(_lib.mgrav_fmm_lists_fill_host(*head, _ptr(pp_off), _ptr(pc_off), _ptr(cc_off),
+                                          *[_ptr(o[k]) for k in ("pp_src", "pp_img", "pp_sub",
+                                                                 "pc_src", "pc_img", "cc_src",
+                                                                 "cc_img")]))
+    npp, npc, ncc = int(pp_off[-1]), int(pc_off[-1]), int(cc_off[-1])
+    return FmmLists(pp_off, o["pp_src"][:npp], o["pp_img"][:npp], o["pp_sub"][:npp], pc_off,
+                    o["pc_src"][:npc], o["pc_img"][:npc], cc_off, o["cc_src"][:ncc],
+                    o["cc_img"][:ncc], int(n_images))
+
+
 # --------------------------------------------------------------------------
 # Device side
 # --------------------------------------------------------------------------
@@ -501,6 +568,10 @@ class Context:
             setattr(p, name, keep[name].data_ptr())
         p.n_pp = int(lists.pp_off[-1])
         p.n_pc = int(lists.pc_off[-1])
+        sub = getattr(lists, "pp_sub", None)
+        if sub is not None:
+            keep["pp_sub"] = t(sub if sub.size else np.zeros(1, np.uint8), np.uint8)
+            p.pp_sub = keep["pp_sub"].data_ptr()
         torch.cuda.synchronize(dev)
         return keep, p
 
@@ -672,6 +743,37 @@ class Context:
         _check(_lib.mgrav_store_active(self._h, st.n, ctypes.byref(s), int(rung_lo),
                                        _P(act.data_ptr())), self._h)
         return act
+
+    def fmm_apply(self, pos_tree_dev, mass_tree_dev, keep: dict, fl_dev: dict, eps: float,
+                  box_L: float, acc, pot, active_dev=None, want_local: bool = False):
+        """The CC / CP part (local expansions) added to acc / pot after a
+        compute: keep holds the bound problem's device tensors (tree), fl_dev
+        the device CC lists (cc_off, cc_src, cc_img)."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        f = Fmm()
+        f.n = int(pos_tree_dev.shape[0])
+        f.n_cell = int(keep["cell_first"].shape[0])
+        f.n_bucket = int(keep["bucket_cell"].shape[0])
+        for k in ("child", "com", "mom", "cell_first", "cell_count", "bucket_cell"):
+            setattr(f, k, keep[k].data_ptr())
+        f.pos = pos_tree_dev.data_ptr()
+        f.mass = mass_tree_dev.data_ptr()
+        f.eps, f.box_L = float(eps), float(box_L)
+        for k in ("cc_off", "cc_src", "cc_img"):
+            setattr(f, k, fl_dev[k].data_ptr())
+        f.active = active_dev.data_ptr() if active_dev is not None else None
+        sz = ctypes.c_size_t(0)
+        _check(_lib.mgrav_fmm_workspace_size(f.n_cell, ctypes.byref(sz)))
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
+        local = torch.empty((f.n_bucket, 56), dtype=torch.float64, device=dev) if want_local \
+            else None
+        self._sync_in()
+        _check(_lib.mgrav_fmm_apply(self._h, ctypes.byref(f), _P(ws.data_ptr()),
+                                    ctypes.c_size_t(ws.numel()), _P(acc.data_ptr()),
+                                    _P(pot.data_ptr()),
+                                    _P(local.data_ptr()) if local is not None else None), self._h)
+        return local
 
     def problem_device(self, dtree, dlists, eps: float, theta: float):
         """A Problem over a DeviceTree and DeviceLists (no host copies);

@@ -228,6 +228,7 @@ struct StageArgs {
     const int64_t* __restrict__ pp_off;
     const int32_t* __restrict__ pp_src;
     const uint8_t* __restrict__ pp_img;
+    const uint8_t* __restrict__ pp_sub;  // nullable: 0 whole leaf, k + 1 its k-th particle
     const int64_t* __restrict__ pc_off;
     Control* ctl;
     float4* pdat;
@@ -379,12 +380,13 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
     if (range_ok) {
         for (int64_t eb = e0 + sl; eb < e1; eb += kStageRound * kStageLanes) {
             int64_t src[kStageRound];
-            int img[kStageRound];
+            int img[kStageRound], sub[kStageRound];
 #pragma unroll
             for (int u = 0; u < kStageRound; ++u) {
                 const int64_t e = eb + u * kStageLanes;
                 src[u] = e < e1 ? int64_t(a.pp_src[e]) : -1;
                 img[u] = e < e1 ? int(a.pp_img[e]) : 0;
+                sub[u] = e < e1 && a.pp_sub ? int(a.pp_sub[e]) : 0;
             }
             CellInfo si[kStageRound];
 #pragma unroll
@@ -396,12 +398,15 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
                 const int64_t e = eb + u * kStageLanes;
                 if (e >= e1) continue;
                 float4 out = make_float4(0.f, 0.f, 0.f, __int_as_float(0));
-                if (sink_ok && img[u] < a.n_images && si[u].count > 0) {
+                if (sink_ok && img[u] < a.n_images && si[u].count > 0 && sub[u] <= si[u].count) {
+                    // a whole source leaf, or one particle of it (same centre)
+                    const int first = sub[u] ? si[u].first + sub[u] - 1 : si[u].first;
+                    const int count = sub[u] ? 1 : si[u].count;
                     out.x = float(si[u].cx + c_shift[img[u]][0] * a.L - ci.cx);
                     out.y = float(si[u].cy + c_shift[img[u]][1] * a.L - ci.cy);
                     out.z = float(si[u].cz + c_shift[img[u]][2] * a.L - ci.cz);
-                    out.w = __uint_as_float(uint32_t(si[u].first) | (uint32_t(si[u].count) << 27));
-                    nsrc += si[u].count;
+                    out.w = __uint_as_float(uint32_t(first) | (uint32_t(count) << 27));
+                    nsrc += count;
                     if (src[u] == s && img[u] == 0) self = 1;
                 } else {
                     bad = 1;
@@ -1714,6 +1719,7 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.pp_off = p.pp_off;
     a.pp_src = p.pp_src;
     a.pp_img = p.pp_img;
+    a.pp_sub = p.pp_sub;
     a.pc_off = p.pc_off;
     char* w = c->ws;
     a.ctl = reinterpret_cast<Control*>(w + c->lay.ctl);
@@ -2655,3 +2661,4 @@ mgrav_status mgrav_set_launch_mode(mgrav_ctx* c, int mode) {
 #include "mlp_api.inc"
 #include "tree_dev.inc"
 #include "store.inc"
+#include "fmm.inc"

@@ -401,3 +401,215 @@ extern "C" mgrav_status mgrav_lists_fill_host(int64_t n_bucket, const int32_t* b
     }
     return MGRAV_OK;
 }
+
+// ---------------------------------------------------------------------
+// Fast-multipole walk (Sec. 3.1): sink cells from the root in
+// node-left-right order, each with the checklist its parent kept.  A
+// source (a cell, or a particle of an opened leaf: opening radius 0, a
+// point box) seen through an image is a CC / CP interaction of the sink
+// when it lies beyond 1.5 RO_sink + RO_source with the boxes at least
+// 2 eps apart; at a bucket sink the rest becomes PP (a particle, or a
+// whole leaf) or PC (the bucket walk's rule) or is opened; at a larger sink
+// a particle or a source smaller than the sink stays for the children,
+// a source at least as large is opened (a leaf into its particles).
+// ---------------------------------------------------------------------
+namespace {
+
+struct FEntry {
+    int32_t idx;   // cell, or tree-order particle
+    uint8_t img;
+    uint8_t part;  // 1: particle `idx`, particle `sub` of leaf `leaf`
+    uint8_t sub;
+    int32_t leaf;
+};
+
+struct FmmArgs {
+    const int64_t* cell_first;
+    const int32_t* cell_count;
+    const int32_t* child;
+    const double *com, *bmax, *bbox, *pos;
+    double theta, eps, L;
+    const int64_t* leaf_no;  // bucket number of each leaf (-1 otherwise)
+    bool fill;
+    int64_t *pp_off, *pc_off, *cc_off;
+    int32_t *pp_src, *pc_src, *cc_src;
+    uint8_t *pp_img, *pp_sub, *pc_img, *cc_img;
+};
+
+// The sink S with checklist `in`; the children's checklist goes to `keep`.
+void fmm_visit(const FmmArgs& w, int64_t S, const std::vector<FEntry>& in,
+               std::vector<FEntry>& keep) {
+    std::vector<FEntry> q(in);
+    keep.clear();
+    const bool leaf = w.child[2 * S] < 0;
+    const double* XS = w.com + 3 * S;
+    const double* sb = w.bbox + 6 * S;
+    const double ro_s = w.bmax[S] / w.theta;
+    const int64_t b = leaf ? w.leaf_no[S] : -1;
+    int64_t kpp = 0, kpc = 0, kcc = 0;
+    for (size_t i = 0; i < q.size(); ++i) {
+        const FEntry e = q[i];
+        double sh[3];
+        image_offset(e.img, w.L, sh);
+        double X[3], lo[3], hi[3], ro, bm;
+        if (e.part) {
+            for (int d = 0; d < 3; ++d) {
+                X[d] = w.pos[3 * int64_t(e.idx) + d] + sh[d];
+                lo[d] = hi[d] = X[d];
+            }
+            ro = bm = 0.0;
+        } else {
+            for (int d = 0; d < 3; ++d) {
+                X[d] = w.com[3 * int64_t(e.idx) + d] + sh[d];
+                lo[d] = w.bbox[6 * int64_t(e.idx) + d] + sh[d];
+                hi[d] = w.bbox[6 * int64_t(e.idx) + 3 + d] + sh[d];
+            }
+            bm = w.bmax[e.idx];
+            ro = bm / w.theta;
+        }
+        const double dx = X[0] - XS[0], dy = X[1] - XS[1], dz = X[2] - XS[2];
+        const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+        double g2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double g = 0.0;
+            if (lo[a] - sb[3 + a] > g) g = lo[a] - sb[3 + a];
+            if (sb[a] - hi[a] > g) g = sb[a] - hi[a];
+            g2 += g * g;
+        }
+        const bool apart = std::sqrt(g2) >= 2.0 * w.eps;
+        if (dist > 1.5 * ro_s + ro && apart) {
+            if (w.fill) {
+                const int64_t k = w.cc_off[S] + kcc;
+                w.cc_src[k] = e.part ? ~e.idx : e.idx;
+                w.cc_img[k] = e.img;
+            }
+            ++kcc;
+        } else if (leaf) {
+            if (e.part || (!(dist > ro + w.bmax[S] && apart) && w.child[2 * e.idx] < 0)) {
+                if (w.fill) {
+                    const int64_t k = w.pp_off[b] + kpp;
+                    w.pp_src[k] = e.part ? e.leaf : e.idx;
+                    w.pp_img[k] = e.img;
+                    w.pp_sub[k] = e.part ? uint8_t(e.sub + 1) : uint8_t(0);
+                }
+                ++kpp;
+            } else if (dist > ro + w.bmax[S] && apart) {
+                if (w.fill) {
+                    const int64_t k = w.pc_off[b] + kpc;
+                    w.pc_src[k] = e.idx;
+                    w.pc_img[k] = e.img;
+                }
+                ++kpc;
+            } else {
+                q.push_back(FEntry{w.child[2 * e.idx], e.img, 0, 0, -1});
+                q.push_back(FEntry{w.child[2 * e.idx + 1], e.img, 0, 0, -1});
+            }
+        } else if (!e.part && bm >= w.bmax[S]) {
+            if (w.child[2 * e.idx] < 0) {
+                const int32_t f = int32_t(w.cell_first[e.idx]);
+                for (int s = 0; s < w.cell_count[e.idx]; ++s)
+                    q.push_back(FEntry{f + s, e.img, 1, uint8_t(s), e.idx});
+            } else {
+                q.push_back(FEntry{w.child[2 * e.idx], e.img, 0, 0, -1});
+                q.push_back(FEntry{w.child[2 * e.idx + 1], e.img, 0, 0, -1});
+            }
+        } else {
+            keep.push_back(e);
+        }
+    }
+    if (!w.fill) {
+        w.cc_off[S + 1] = kcc;
+        if (leaf) {
+            w.pp_off[b + 1] = kpp;
+            w.pc_off[b + 1] = kpc;
+        }
+    }
+}
+
+// Depth-first over the sinks with an explicit stack; subtrees of more than
+// `task_cells` cells become OpenMP tasks (each writes only its own cells'
+// and buckets' entries).
+void fmm_subtree(const FmmArgs& w, int64_t root, std::vector<FEntry> list) {
+    struct Frame {
+        int64_t S;
+        std::vector<FEntry> list;
+    };
+    std::vector<Frame> stack;
+    stack.push_back(Frame{root, std::move(list)});
+    std::vector<FEntry> keep;
+    while (!stack.empty()) {
+        Frame f = std::move(stack.back());
+        stack.pop_back();
+        fmm_visit(w, f.S, f.list, keep);
+        if (w.child[2 * f.S] < 0) continue;
+        const int64_t c0 = w.child[2 * f.S], c1 = w.child[2 * f.S + 1];
+        if (w.cell_count[f.S] > 65536) {
+#pragma omp task firstprivate(c1, keep) shared(w)
+            fmm_subtree(w, c1, keep);
+#pragma omp task firstprivate(c0, keep) shared(w)
+            fmm_subtree(w, c0, keep);
+        } else {
+            stack.push_back(Frame{c1, keep});
+            stack.push_back(Frame{c0, keep});
+        }
+    }
+}
+
+mgrav_status fmm_run(FmmArgs& w, int64_t n_cell, int n_images) {
+    std::vector<int64_t> leaf_no(n_cell, -1);
+    int64_t nb = 0;
+    for (int64_t c = 0; c < n_cell; ++c)
+        if (w.child[2 * c] < 0) leaf_no[c] = nb++;
+    w.leaf_no = leaf_no.data();
+    std::vector<FEntry> root;
+    for (int i = 0; i < n_images; ++i) root.push_back(FEntry{0, uint8_t(i), 0, 0, -1});
+    if (!w.fill) {
+        w.pp_off[0] = w.pc_off[0] = w.cc_off[0] = 0;
+    }
+#pragma omp parallel
+#pragma omp single
+    fmm_subtree(w, 0, root);
+    if (!w.fill) {
+        for (int64_t b = 0; b < nb; ++b) {
+            w.pp_off[b + 1] += w.pp_off[b];
+            w.pc_off[b + 1] += w.pc_off[b];
+        }
+        for (int64_t c = 0; c < n_cell; ++c) w.cc_off[c + 1] += w.cc_off[c];
+    }
+    return MGRAV_OK;
+}
+
+}  // namespace
+
+extern "C" mgrav_status mgrav_fmm_lists_count_host(
+    int64_t n_cell, const int64_t* cell_first, const int32_t* cell_count, const int32_t* child,
+    const double* com, const double* bmax, const double* bbox, const double* pos, double theta,
+    double eps, double L, int n_images, int64_t* pp_off, int64_t* pc_off, int64_t* cc_off) {
+    mgrav_status st = check_walk_args(theta, eps, L, n_images);
+    if (st != MGRAV_OK) return st;
+    if (n_cell < 1 || !cell_first || !cell_count || !child || !com || !bmax || !bbox || !pos ||
+        !pp_off || !pc_off || !cc_off)
+        return mgrav_internal::set_host_error(MGRAV_ERR_INVALID_ARG, "fmm lists: null pointer");
+    FmmArgs w{cell_first, cell_count, child, com, bmax, bbox, pos, theta, eps, L, nullptr, false,
+              pp_off, pc_off, cc_off, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+              nullptr};
+    return fmm_run(w, n_cell, n_images);
+}
+
+extern "C" mgrav_status mgrav_fmm_lists_fill_host(
+    int64_t n_cell, const int64_t* cell_first, const int32_t* cell_count, const int32_t* child,
+    const double* com, const double* bmax, const double* bbox, const double* pos, double theta,
+    double eps, double L, int n_images, const int64_t* pp_off, const int64_t* pc_off,
+    const int64_t* cc_off, int32_t* pp_src, uint8_t* pp_img, uint8_t* pp_sub, int32_t* pc_src,
+    uint8_t* pc_img, int32_t* cc_src, uint8_t* cc_img) {
+    mgrav_status st = check_walk_args(theta, eps, L, n_images);
+    if (st != MGRAV_OK) return st;
+    if (n_cell < 1 || !cell_first || !cell_count || !child || !com || !bmax || !bbox || !pos ||
+        !pp_off || !pc_off || !cc_off || !pp_src || !pp_img || !pp_sub || !pc_src || !pc_img ||
+        !cc_src || !cc_img)
+        return mgrav_internal::set_host_error(MGRAV_ERR_INVALID_ARG, "fmm lists: null pointer");
+    FmmArgs w{cell_first, cell_count, child, com, bmax, bbox, pos, theta, eps, L, nullptr, true,
+              const_cast<int64_t*>(pp_off), const_cast<int64_t*>(pc_off),
+              const_cast<int64_t*>(cc_off), pp_src, pc_src, cc_src, pp_img, pp_sub, pc_img, cc_img};
+    return fmm_run(w, n_cell, n_images);
+}

@@ -137,7 +137,8 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("gcc not available")
     pairs = [("mgrav_problem", mg.Problem), ("mgrav_ewald", mg.EwaldConfig),
              ("mgrav_stats", mg.Stats), ("mgrav_train_cfg", mg.TrainConfig),
-             ("mgrav_tree_dev", mg.TreeDev), ("mgrav_walk", mg.Walk), ("mgrav_store", mg.Store)]
+             ("mgrav_tree_dev", mg.TreeDev), ("mgrav_walk", mg.Walk), ("mgrav_store", mg.Store),
+             ("mgrav_fmm", mg.Fmm)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mgrav.h"',
              "int main(void) {"]
     for cname, cls in pairs:
@@ -202,3 +203,19 @@ def test_store_calls_refuse_bad_arguments_on_the_host():
     assert mg._lib.mgrav_store_encode(None, 10, None, None, 1, ctypes.byref(st)) == \
         mg.ERR_INVALID_ARG
     assert mg._lib.mgrav_store_drift(None, 10, ctypes.byref(st), 0.1, 1) == mg.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_host_fmm_lists_equal_oracle(sets, k):
+    """The library's fast-multipole walk (C++, tasks over subtrees) gives the
+    oracle's lists entry for entry."""
+    ps = sets[k]
+    t = mg.tree_build(ps.pos, ps.mass, ps.box_L, 16)
+    pt = ps.pos[t.perm]
+    lg = mg.fmm_lists_build(t, pt, 0.7, ps.eps)
+    to = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    lo = oracle.build_fmm_lists(to, pt, 0.7, ps.eps)
+    for f in ("pp_off", "pp_src", "pp_img", "pp_sub", "pc_off", "pc_src", "pc_img", "cc_off",
+              "cc_src", "cc_img"):
+        assert np.array_equal(getattr(lg, f), getattr(lo, f)), f
+    assert lo.cc_src.size > 0 and (lo.cc_src < 0).any() and (lo.pp_sub > 0).any()
