@@ -48,6 +48,8 @@ def parse():
                     help="config 5: about this many sink buckets in the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle (CPU baseline; config 5: the sampled parity)")
+    ap.add_argument("--no-fmm", action="store_true",
+                    help="config 5: skip the fast-multipole leg (128^3 clustered set)")
     ap.add_argument("--no-kdk", action="store_true",
                     help="config 5: skip the integrator leg (one timed KDK base step)")
     ap.add_argument("--kdk-rungs", type=int, default=3)
@@ -673,6 +675,8 @@ def substeps(args):
         out["cpu_baseline"] = cpu_baseline_sample(sample, pos_t, mass_t, eps, a_sample,
                                                   p_sample, st.n_pp_interactions +
                                                   st.n_pc_interactions)
+    if not args.no_fmm:
+        out["fmm"] = fmm_leg(ctx, args)
     if not args.no_kdk:
         del tensors, prob, ws, lists, tree
         torch.cuda.empty_cache()
@@ -680,6 +684,77 @@ def substeps(args):
     ctx.close()
     out["bench_seconds"] = time.perf_counter() - t_all
     print(json.dumps(out), flush=True)
+
+
+def fmm_leg(ctx, args):
+    """The fast-multipole form (CC / CP interactions into local expansions
+    about the sink cells, Sec. 3.1) against the bucket walk on the 128^3
+    clustered set (2 097 152 particles, exact Ewald): the same tree, host
+    walks for both list kinds, each step timed as bind + compute (+ the
+    expansions' CC / CP, shift and evaluation for the FMM)."""
+    import numpy as np
+    import torch
+
+    import paper_1609_08621_amd as mg
+    import workloads
+    cfg = workloads.CONFIGS[3]
+    ps = workloads.make(3)
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    tree = mg.tree_build(ps.pos, ps.mass, ps.box_L, 16)
+    pt, mt = ps.pos[tree.perm], ps.mass[tree.perm]
+    lists = mg.lists_build(tree, cfg.theta, ps.eps)
+    t_bucket = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fl = mg.fmm_lists_build(tree, pt, cfg.theta, ps.eps)
+    t_fmm_walk = time.perf_counter() - t0
+    res = {}
+    acc_out = {}
+    for label, ls in (("bucket", lists), ("fmm", fl)):
+        keep, p = ctx.upload(pt, mt, tree, ls, ps.eps, cfg.theta)
+        ws = torch.empty(ctx.workspace_size(p), dtype=torch.uint8, device=dev)
+        acc = torch.zeros(3 * ps.n, dtype=torch.float32, device=dev)
+        pot = torch.zeros(ps.n, dtype=torch.float32, device=dev)
+        fl_dev = None
+        if label == "fmm":
+            fl_dev = {k: torch.from_numpy(getattr(fl, k)).to(dev)
+                      for k in ("cc_off", "cc_src", "cc_img")}
+
+        def step():
+            ctx.bind(p, keep, ws)
+            ctx.compute(acc, pot)
+            st = ctx.wait(120.0)
+            if fl_dev is not None:
+                ctx.fmm_apply(keep["pos"], keep["mass"], keep, fl_dev, ps.eps, ps.box_L, acc,
+                              pot)
+            return st
+        step()
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 10))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        res[label] = {"ms_per_step": ms, "n_pp_interactions": st.n_pp_interactions,
+                      "n_pc_interactions": st.n_pc_interactions}
+        acc_out[label] = acc.view(3, -1).t().double().cpu().numpy()
+        del keep, ws, acc, pot
+    res["fmm"]["n_cc_cp_entries"] = int(fl.cc_src.size)
+    res["fmm"]["n_cp_entries"] = int((fl.cc_src < 0).sum())
+    a, b = acc_out["fmm"], acc_out["bucket"]
+    diff = float(np.sqrt(np.mean(np.sum((a - b) ** 2, 1) / np.sum(b ** 2, 1))))
+    log(f"fmm: bucket walk step {res['bucket']['ms_per_step']:.2f} ms "
+        f"(pp {res['bucket']['n_pp_interactions']}, pc {res['bucket']['n_pc_interactions']}); "
+        f"fmm step {res['fmm']['ms_per_step']:.2f} ms (pp {res['fmm']['n_pp_interactions']}, "
+        f"pc {res['fmm']['n_pc_interactions']}, cc+cp entries {fl.cc_src.size}); rms difference "
+        f"of the two methods {diff:.2e}; host walks {t_bucket:.1f} s (tree + bucket lists), "
+        f"{t_fmm_walk:.1f} s (fmm lists)")
+    return {"workload": f"{cfg.name} (n={ps.n}, theta {cfg.theta}, exact Ewald)",
+            "bucket_walk": res["bucket"], "fmm": res["fmm"],
+            "rms_rel_difference_fmm_vs_bucket_walk": diff,
+            "host_seconds_tree_and_bucket_lists": t_bucket,
+            "host_seconds_fmm_lists": t_fmm_walk}
 
 
 def kdk_leg(ctx, store, m_uniform, eps, cfg, amag, rung_max):

@@ -223,17 +223,20 @@ typedef struct {
     const int32_t *sink_cell;
 } mgrav_walk;
 
-/* Device workspace of the walk (96 bytes per cell, 16 per sink). */
+/* Device workspace of the walk (96 bytes per cell, 24 per sink, and the
+ * overflow pass's rings: 64 x 8 x (2^14 .. 2^20) bytes). */
 mgrav_status mgrav_lists_workspace_size(int64_t n_cell, int64_t n_sink, size_t *bytes);
 
 /* Pass 1: pp_off[n_sink + 1] and pc_off[n_sink + 1] (device) receive the
  * CSR offsets of the lists; *n_pp and *n_pc (host, nullable) their
  * totals.  Pass 2 fills pp_src, pp_img, pc_src, pc_img (device) in
  * checklist order, with the offsets of pass 1 and the same workspace
- * contents or a new one.  Each sink's checklist runs in a ring of 1024
- * entries (NO_MEMORY if one outgrows it; far more than the tens of
- * entries a checklist holds here).  BAD_TREE for a cell index outside the
- * tree, INVALID_ARG for bad scalars.  Blocking. */
+ * contents or a new one.  Each sink's checklist runs in an LDS ring of
+ * 1024 entries; sinks whose checklist outgrows it (sparse buckets of a
+ * very active tree among dense fixed cells) are walked again by a second
+ * pass with a ring of up to 2^20 entries in the workspace (NO_MEMORY if
+ * one outgrows that too).  BAD_TREE for a cell index outside the tree,
+ * INVALID_ARG for bad scalars.  Blocking. */
 mgrav_status mgrav_lists_count(mgrav_ctx *ctx, const mgrav_walk *walk, void *workspace,
                                size_t bytes, int64_t *pp_off, int64_t *pc_off, int64_t *n_pp,
                                int64_t *n_pc);

@@ -201,3 +201,29 @@ def test_device_tree_errors(mg_ctx):
     td = ctx.tree_build(_dev(ps.pos), _dev(ps.mass), ps.box_L, 16)
     to = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
     assert np.array_equal(td.to_host().perm, to.perm)
+
+
+def test_long_checklists_take_the_overflow_pass(mg_ctx):
+    """Clustered 48^3 with 0.2 % of the particles, scattered, in the very
+    active tree: its buckets are wide, their checklists among the dense
+    fixed cells grow past the walk's LDS ring (1183 entries at the peak on
+    the host), and the second pass with the global ring must give the
+    oracle's lists all the same."""
+    mg, ctx = mg_ctx
+    ps = workloads.make(3, scale_n1d=48)
+    rng = np.random.default_rng(1)
+    g = np.zeros(ps.n, np.uint8)
+    g[rng.choice(ps.n, int(0.002 * ps.n), replace=False)] = 1
+    _case(f"device forest clustered_48 n={ps.n} active={int(g.sum())} (long checklists)")
+    td = ctx.tree_build(_dev(ps.pos, np.float64), _dev(ps.mass, np.float64), ps.box_L, 16,
+                        group_dev=_dev(g))
+    dl = ctx.lists_build(td, 0.7, ps.eps, sinks="second")
+    fo = oracle.build_forest(ps.pos, ps.mass, ps.box_L, g)
+    sinks = np.arange(td.n_bucket_first, fo.n_bucket)
+    lo = oracle.build_lists(fo, 0.7, ps.eps, sinks=sinks)
+    lh = dl.to_host()
+    for f in ("pp_off", "pc_off"):
+        assert np.array_equal(getattr(lh, f)[td.n_bucket_first:], getattr(lo, f)), f
+    for f in ("pp_src", "pp_img", "pc_src", "pc_img"):
+        assert np.array_equal(getattr(lh, f), getattr(lo, f)), f
+    print(f"  sinks={sinks.size} pp={lo.pp_src.size} pc={lo.pc_src.size}", flush=True)
