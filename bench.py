@@ -248,7 +248,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_interact_lattice_64cubed_counters.json")
+def counters_file(workload: str) -> str:
+    """The committed counter summary of the PP + PC kernel on a workload
+    (profiles/k_interact_<workload without _periodic>_counters.json)."""
+    short = workload[:-len("_periodic")] if workload.endswith("_periodic") else workload
+    return os.path.join(ROOT, "profiles", f"k_interact_{short}_counters.json")
 
 
 def interact_source_digest() -> str:
@@ -266,8 +270,9 @@ def interact_traffic(workload: str, pp_chunk: int, waves: int, prefetch: int):
     the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
     scaled by a copy of known size), or None when the summary is missing,
     for another workload or variant, or taken on different kernel source."""
+    path = counters_file(workload)
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -281,7 +286,7 @@ def interact_traffic(workload: str, pp_chunk: int, waves: int, prefetch: int):
             "fetch_kib_raw": var["fetch_kib_per_dispatch"],
             "write_kib_raw": var["write_kib_per_dispatch"],
             "fetch_factor": rec["fetch_factor"], "write_factor": rec["write_factor"],
-            "variant": key, "source": os.path.relpath(COUNTERS, ROOT)}
+            "variant": key, "source": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(args, ps, cfg, tree, pos_t, mass_t, acc_dev, pot_dev):
@@ -460,6 +465,16 @@ def substeps(args):
     pot = torch.zeros(n, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     log(f"workspace {ws.numel() / 2**30:.1f} GiB")
+    if args.calibrate_copy_mib > 0:
+        # a plain device copy of known size: the reference of the HBM
+        # traffic counters (FETCH_SIZE, WRITE_SIZE)
+        src = torch.ones((args.calibrate_copy_mib << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
+        del src, dst
     sample = None
     if not args.no_cpu_baseline:
         stride = max(1, n_bucket // args.cpu_buckets)
