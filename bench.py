@@ -626,6 +626,37 @@ def substeps(args):
     ctx.set_active(None)
     del tensors_q, prob_q
 
+    # layouts of the PP + PC kernel's work queue: cost order against
+    # locality order (per-die segments in tree order); the kernel's span,
+    # mean of 3 waited steps after one untimed
+    queue_rows = []
+    for frac in (1.0, 0.1, 0.01):
+        mask = None if frac == 1.0 else torch.from_numpy(
+            workloads.active_by_acceleration(amag, frac)).to(dev)
+        ms, used = {}, None
+        for label, order in (("lpt", mg.QUEUE_LPT), ("local", mg.QUEUE_LOCAL),
+                             ("auto", mg.QUEUE_AUTO)):
+            ctx.set_queue_order(order)
+            ks = []
+            for rep in range(4):
+                ctx.bind(prob, tensors, ws)
+                ctx.set_ewald(**ew_cfg)
+                ctx.set_active(mask)
+                ctx.compute(acc, pot)
+                st_q = ctx.wait(300.0)
+                if rep:
+                    ks.append(st_q.ms_interact)
+            ms[label] = float(np.mean(ks))
+            if order == mg.QUEUE_AUTO:
+                used = "local" if st_q.queue_local else "lpt"
+        queue_rows.append({"active_fraction": frac, "ms_interact_lpt": ms["lpt"],
+                           "ms_interact_local": ms["local"], "ms_interact_auto": ms["auto"],
+                           "auto_layout": used})
+        log(f"queue order: active {frac:.0%}: kernel {ms['lpt']:.2f} ms (cost order), "
+            f"{ms['local']:.2f} ms (locality), auto = {used}")
+    ctx.set_queue_order(mg.QUEUE_AUTO)
+    ctx.set_active(None)
+
     st, flops, k_ms, steps = head
     achieved = flops / (k_ms * 1e-3) / 1e12
     kname = (f"k_interact<{tuned['pp_chunk']}, {tuned['waves_per_simd']}, "
@@ -671,6 +702,11 @@ def substeps(args):
                             "copy-calibrated)",
         },
         "substeps": rows,
+        "queue_order": {
+            "note": "PP + PC kernel span (ms) per work-queue layout: cost order (longest first) "
+                    "against locality order (costliest buckets first, the rest in tree order "
+                    "in one segment per die); the steps above use the automatic choice",
+            "rows": queue_rows},
         "store_positions": {
             "note": "positions read as the 28-byte store's 32-bit integers (12 B per particle, "
                     "equal masses without an array) against double positions + masses (32 B)",

@@ -587,6 +587,9 @@ typedef struct {
                                  /* ran, 0 = the surrogate was accepted      */
     int64_t ewald_samples;       /* SURROGATE_FALLBACK: active sample size   */
     double ewald_sample_err;     /* SURROGATE_FALLBACK: err of the sample    */
+    int queue_local;             /* 1: the work queue was laid out for       */
+                                 /* locality (mgrav_set_queue_order)         */
+    int queue_pad;
 } mgrav_stats;
 
 /* Wait for the context's work with a watchdog (mgrav_watchdog_poll on an
@@ -720,6 +723,21 @@ mgrav_status mgrav_autotune(mgrav_ctx *ctx, float *acc, float *pot, const char *
  * used).  INVALID_ARG for another value. */
 enum { MGRAV_LAUNCH_GRAPH = 0, MGRAV_LAUNCH_DIRECT = 1 };
 mgrav_status mgrav_set_launch_mode(mgrav_ctx *ctx, int mode);
+
+/* Order of the PP + PC kernel's work queue (Sec. 3.3: the persistent
+ * kernel pulls sink buckets from one queue).  MGRAV_QUEUE_LPT: the active
+ * buckets by estimated cost, most expensive first (in factors of 2), so the
+ * kernel ends on short items.  MGRAV_QUEUE_LOCAL: only the buckets within a
+ * factor 8 of the most expensive stay in front, in that order; the rest
+ * follow in bucket (tree) order, cut into one segment per die of the chip,
+ * each drained first by the wavefronts of its own die (then by the others),
+ * so that the buckets one L2 serves at the same time share their source
+ * cells.  MGRAV_QUEUE_AUTO (default): LOCAL when no mask is set and the
+ * problem has 131072 buckets or more, else LPT.  Results are identical under every order (mgrav_stats
+ * queue_local tells which layout the last compute used); INVALID_ARG for
+ * another value.  Applies from the next compute. */
+enum { MGRAV_QUEUE_AUTO = 0, MGRAV_QUEUE_LPT = 1, MGRAV_QUEUE_LOCAL = 2 };
+mgrav_status mgrav_set_queue_order(mgrav_ctx *ctx, int order);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,7 @@ OK, ERR_INVALID_ARG, ERR_BAD_TREE, ERR_BAD_LIST, ERR_DEVICE, ERR_NO_MEMORY, \
 PART_PP, PART_PC, PART_EWALD, PART_ALL = 1, 2, 4, 7
 EWALD_NONE, EWALD_EXACT, EWALD_SURROGATE, EWALD_SURROGATE_FALLBACK = 0, 1, 2, 3
 LAUNCH_GRAPH, LAUNCH_DIRECT = 0, 1
+QUEUE_AUTO, QUEUE_LPT, QUEUE_LOCAL = 0, 1, 2
 MAX_BUCKET = 16
 STATIC_WORKSPACE_BYTES = 64 << 20  # mgrav_bind_static's workspace per GPU
 
@@ -75,7 +76,8 @@ class Stats(ctypes.Structure):
                 ("n_active_buckets", _I64), ("n_active_particles", _I64),
                 ("ms_total", _D), ("ms_interact", _D), ("ms_ewald", _D),
                 ("graph_replay", _I), ("interact_variant", _I), ("graph_error", _I),
-                ("ewald_fallback", _I), ("ewald_samples", _I64), ("ewald_sample_err", _D)]
+                ("ewald_fallback", _I), ("ewald_samples", _I64), ("ewald_sample_err", _D),
+                ("queue_local", _I), ("queue_pad", _I)]
 
 
 class TreeDev(ctypes.Structure):
@@ -172,6 +174,8 @@ def _declare():
     L.mgrav_autotune.argtypes = [_P, _P, _P, ctypes.c_char_p, _D, ctypes.POINTER(_I), _P]
     L.mgrav_set_launch_mode.restype = _I
     L.mgrav_set_launch_mode.argtypes = [_P, _I]
+    L.mgrav_set_queue_order.restype = _I
+    L.mgrav_set_queue_order.argtypes = [_P, _I]
     L.mgrav_tree_workspace_size.restype = _I
     L.mgrav_tree_workspace_size.argtypes = [_I64, _I, _I64, ctypes.POINTER(ctypes.c_size_t)]
     L.mgrav_tree_build.restype = _I
@@ -226,7 +230,7 @@ EXPORTS = (
     "mgrav_ewald_psi", "mgrav_mlp_workspace_size", "mgrav_mlp_attach", "mgrav_mlp_set_weights",
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
     "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
-    "mgrav_autotune", "mgrav_set_launch_mode", "mgrav_watchdog_poll",
+    "mgrav_autotune", "mgrav_set_launch_mode", "mgrav_set_queue_order", "mgrav_watchdog_poll",
     "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_lists_workspace_size",
     "mgrav_lists_count", "mgrav_lists_fill", "mgrav_store_encode", "mgrav_store_decode",
     "mgrav_store_permute", "mgrav_store_drift", "mgrav_store_kick", "mgrav_store_rungs",
@@ -846,6 +850,11 @@ class Context:
     def set_launch_mode(self, mode: int):
         """LAUNCH_GRAPH (one HIP graph per compute) or LAUNCH_DIRECT."""
         _check(_lib.mgrav_set_launch_mode(self._h, int(mode)), self._h)
+
+    def set_queue_order(self, order: int):
+        """QUEUE_AUTO, QUEUE_LPT (most expensive buckets first) or QUEUE_LOCAL
+        (expensive ones first, the rest in tree order per die)."""
+        _check(_lib.mgrav_set_queue_order(self._h, int(order)), self._h)
 
     def set_interact_variant(self, variant: int):
         _check(_lib.mgrav_set_interact_variant(self._h, int(variant)), self._h)

@@ -67,6 +67,20 @@ constexpr int kErrTree = 1, kErrList = 2, kErrParticle = 4;
 
 // Control block at the start of the workspace.
 constexpr int kCostBins = 64;
+constexpr int kXcd = 8;  // accelerator dies of the chip, each with its own L2
+
+// Queue layouts (RunArgs::queue_order; MGRAV_QUEUE_* of the header):
+// longest processing time first over the whole queue, or locality first:
+// the few most expensive buckets (within a factor 8 of the costliest) in
+// that order, then the rest in bucket (tree) order cut into kXcd
+// segments, one per die, so that the buckets one L2 serves at a time are
+// neighbours in space and share most of their source cells.  Automatic:
+// locality when every particle is active and there are kLocalityMinItems
+// buckets or more (the buckets of a substep's mask are scattered through
+// the tree and share less; there cost order measured as fast or faster).
+constexpr int kQueueAuto = 0, kQueueLpt = 1, kQueueLocal = 2;
+constexpr int kLocalityMinItems = 1 << 17;
+constexpr int kTopBins = 3;  // cost bins (factors of 2) that stay in front
 
 struct Control {
     int err;
@@ -87,6 +101,10 @@ struct Control {
     int sel_done;                   // k_select blocks finished (the last one orders the bins)
     int waves_done;                 // k_interact waves finished (the last one stamps t_k1)
     unsigned long long t_k0, t_k1;  // k_interact's first claim and last exit, device wall clock
+    int order_local;                // queue laid out for locality (set by k_select)
+    int n_top;                      // queue slots before the per-die segments (all if LPT)
+    int front_lo;                   // cost bins >= this one are in LPT order in front
+    int seg_head[kXcd];             // next slot of each per-die segment
 };
 
 // Per-compute fields back to zero: at the end of every compute (after the
@@ -104,8 +122,12 @@ __device__ void reset_compute_counters(Control* ctl) {
         ctl->sel_done = 0;
         ctl->waves_done = 0;
         ctl->t_k0 = ctl->t_k1 = 0;
+        ctl->order_local = 0;
+        ctl->n_top = 0;
+        ctl->front_lo = 0;
     }
     for (int q = threadIdx.x; q < kCostBins; q += blockDim.x) ctl->bin_count[q] = 0;
+    for (int q = threadIdx.x; q < kXcd; q += blockDim.x) ctl->seg_head[q] = 0;
 }
 
 // Image shifts in units of L: id 0 the box, 1..26 lexicographic {-1,0,1}^3.
@@ -462,6 +484,7 @@ struct RunArgs {
     float eps2;
     int parts;
     int* plist;  // with a mask: the active particles, for the Ewald kernels
+    int queue_order;  // kQueueAuto, kQueueLpt or kQueueLocal
 };
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -565,7 +588,8 @@ __global__ void __launch_bounds__(kSelectThreads) k_select(RunArgs a) {
     }
     // the last block to finish lays out the queue: most expensive cost bins
     // first (longest processing time first, to within a factor 2), so the
-    // persistent kernel ends on short items
+    // persistent kernel ends on short items; or, for locality, only the top
+    // kTopBins bins so, and the rest in bucket order behind them
     __syncthreads();  // this block's bin counts are added
     if (threadIdx.x == 0) {
         __threadfence();
@@ -578,34 +602,63 @@ __global__ void __launch_bounds__(kSelectThreads) k_select(RunArgs a) {
         hist[threadIdx.x] = __atomic_load_n(&a.ctl->bin_count[threadIdx.x], __ATOMIC_RELAXED);
     __syncthreads();
     if (threadIdx.x == 0) {
-        int off = 0;
+        int total = 0, top = -1;
         for (int q = kCostBins - 1; q >= 0; --q) {
+            total += hist[q];
+            if (top < 0 && hist[q] > 0) top = q;
+        }
+        const bool local = a.queue_order == kQueueLocal ||
+                           (a.queue_order == kQueueAuto && a.active == nullptr &&
+                            total >= kLocalityMinItems);
+        const int lo = local && top >= kTopBins ? top - kTopBins + 1 : 0;  // LPT: bins >= lo
+        int off = 0;
+        for (int q = kCostBins - 1; q >= 0 && q >= lo; --q) {
             a.ctl->bin_cursor[q] = off;
             off += hist[q];
         }
-        a.ctl->n_items = off;
+        a.ctl->bin_cursor[0] = lo > 0 ? off : a.ctl->bin_cursor[0];  // the shared range
+        a.ctl->front_lo = lo;
+        a.ctl->n_top = local ? off : total;
+        a.ctl->order_local = local ? 1 : 0;
+        a.ctl->n_items = total;
     }
 }
 
 // Block-aggregated scatter: one global atomic per (block, bin) reserves a
-// range of queue slots; ranks inside the block come from LDS atomics.
+// range of queue slots; ranks inside the block come from LDS atomics.  In
+// the locality layout the bins below the top ones share one range, and
+// the block's buckets keep their order in it (ranks from a block scan).
 constexpr int kScatterThreads = 1024;
 __global__ void __launch_bounds__(kScatterThreads) k_order_scatter(RunArgs a) {
     __shared__ int cnt[kCostBins];
     __shared__ int base[kCostBins];
+    __shared__ int wtot[kScatterThreads / kWave];
+    __shared__ int run_base;
     if (threadIdx.x < kCostBins) cnt[threadIdx.x] = 0;
+    const int front_lo = a.ctl->front_lo;  // set by k_select (0: every bin in front)
     __syncthreads();
     const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int bin = -1, rank = 0;
-    if (b < a.n_bucket) {
-        bin = a.bins[b];
-        if (bin >= 0) rank = atomicAdd(&cnt[bin], 1);
-    }
+    if (b < a.n_bucket) bin = a.bins[b];
+    const bool front = bin >= 0 && bin >= front_lo;
+    if (front) rank = atomicAdd(&cnt[bin], 1);
+    // ranks of the shared range, in bucket order
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int in_run = bin >= 0 && !front ? 1 : 0;
+    const int incl = wave_incl_scan(in_run, lane);
+    if (lane == kWave - 1) wtot[w] = incl;
     __syncthreads();
     if (threadIdx.x < kCostBins && cnt[threadIdx.x] > 0)
         base[threadIdx.x] = atomicAdd(&a.ctl->bin_cursor[threadIdx.x], cnt[threadIdx.x]);
+    int before = 0, total = 0;
+    for (int q = 0; q < kScatterThreads / kWave; ++q) {
+        before += q < w ? wtot[q] : 0;
+        total += wtot[q];
+    }
+    if (threadIdx.x == 0 && total > 0) run_base = atomicAdd(&a.ctl->bin_cursor[0], total);
     __syncthreads();
-    if (bin >= 0) a.items[base[bin] + rank] = int(b);
+    if (front) a.items[base[bin] + rank] = int(b);
+    if (in_run) a.items[run_base + before + incl - 1] = int(b);
 }
 
 // Order-4 PC expansion of one cell at one point, float.
@@ -790,12 +843,56 @@ __device__ __forceinline__ int sink_count(int n) {
     return n;
 }
 
+// A wavefront's place in the work queue: the front (one head for all), then
+// its die's segment, then the other dies' segments in turn, each until it
+// runs dry.  Only lane 0's copy is used.
+struct QueueCursor {
+    int phase;  // 0: front; 1: segments
+    int seg;    // segment being drained
+    int tries;  // segments found empty
+};
+
+// Claims a queue slot of the cursor's current range (its result is read
+// later, by queue_resolve, so the atomic's latency hides behind an item).
+__device__ __forceinline__ int queue_issue(Control* ctl, const QueueCursor& q) {
+    return atomicAdd(q.phase == 0 ? &ctl->head : &ctl->seg_head[q.seg], 1);
+}
+
+// The item of a claim, moving on to the next range while the current one
+// is empty; n_items when every range is.
+__device__ int queue_resolve(Control* ctl, QueueCursor& q, int raw, int n_top, int n_items,
+                             bool local) {
+    for (;;) {
+        if (q.phase == 0) {
+            if (raw < n_top) return raw;
+            if (!local) return n_items;
+            q.phase = 1;
+        } else {
+            const int64_t span = int64_t(n_items) - n_top;
+            const int lo = n_top + int(span * q.seg / kXcd);
+            const int hi = n_top + int(span * (q.seg + 1) / kXcd);
+            if (raw < hi - lo) return lo + raw;
+            if (++q.tries == kXcd) return n_items;
+            q.seg = (q.seg + 1) % kXcd;
+        }
+        raw = atomicAdd(&ctl->seg_head[q.seg], 1);
+    }
+}
+
+// Register slot s of a work item's sinks holds sink slot_sink(s): the even
+// sinks fill slots 0..7 and the odd ones slots 8..15, so that the sinks of
+// any bucket split evenly between the two halves of the slot range (the
+// split last PC chunk below gives each half of the wavefront one half).
+__device__ __forceinline__ constexpr int slot_sink(int s) {
+    return s < kBucket / 2 ? 2 * s : 2 * (s - kBucket / 2) + 1;
+}
+
 // Persistent PP + PC kernel.  One wavefront per work item (a sink bucket
 // of up to 16 particles).  The sink particles are wave-uniform (scalar
 // registers); lanes own sources: PP source particles expanded into LDS,
 // PC cells' coefficient records in vector registers.  Each lane keeps
 // 16 x 4 partial sums; a transposing butterfly reduction leaves lane l
-// with component l&3 of sink l>>2.
+// with component l&3 of the sink in slot l>>2.
 template <int kChunk, int kWaves, bool kPrefetch>
 __global__ void __launch_bounds__(kWave)
     __attribute__((amdgpu_waves_per_eu(kWaves, 8))) k_interact(RunArgs a) {
@@ -805,10 +902,17 @@ __global__ void __launch_bounds__(kWave)
     __shared__ int4 etab[kChunk];    // per PP entry of a fill: LDS base, count, first
     __shared__ float4 edel[kChunk];  // per PP entry of a fill: source-sink offset
     const int lane = threadIdx.x;
+    // fixed by earlier kernels
     const int n_items = __builtin_amdgcn_readfirstlane(
-        __atomic_load_n(&a.ctl->n_items, __ATOMIC_RELAXED));  // fixed by earlier kernels
+        __atomic_load_n(&a.ctl->n_items, __ATOMIC_RELAXED));
+    const int n_top =
+        __builtin_amdgcn_readfirstlane(__atomic_load_n(&a.ctl->n_top, __ATOMIC_RELAXED));
+    const bool local =
+        __builtin_amdgcn_readfirstlane(__atomic_load_n(&a.ctl->order_local, __ATOMIC_RELAXED));
+    // single-wave blocks go to the dies in turn: block b runs on die b mod 8
+    QueueCursor qc{0, int(blockIdx.x % kXcd), 0};
     int item = 0;
-    if (lane == 0) item = atomicAdd(&a.ctl->head, 1);
+    if (lane == 0) item = queue_resolve(a.ctl, qc, queue_issue(a.ctl, qc), n_top, n_items, local);
     item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
     // the kernel's span on the device wall clock: from the first claim to the
     // exit of the last wave (every wave exits right after its last item)
@@ -817,12 +921,13 @@ __global__ void __launch_bounds__(kWave)
         if (item >= n_items) break;
         // claim the next queue slot now; its latency hides behind this item
         int next = 0;
-        if (lane == 0) next = atomicAdd(&a.ctl->head, 1);
+        if (lane == 0) next = queue_issue(a.ctl, qc);
         const int b = load_uniform(a.items, item);
         const BucketWork wk = load_uniform(a.work, b);
         const int first = wk.first;
         const int nsink = wk.nsink;
         if (nsink <= 0) {
+            if (lane == 0) next = queue_resolve(a.ctl, qc, next, n_top, n_items, local);
             item = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
             continue;
         }
@@ -846,7 +951,8 @@ __global__ void __launch_bounds__(kWave)
         float sx[kBucket], sy[kBucket], sz[kBucket];
 #pragma unroll
         for (int i = 0; i < kBucket; ++i) {
-            const int p = first + (i < nsink ? i : nsink - 1);
+            const int k = slot_sink(i);
+            const int p = first + (k < nsink ? k : nsink - 1);
             const float4 q = kSinksInVgprs ? a.pdat[p] : load_uniform(a.pdat, p);
             sx[i] = q.x;
             sy[i] = q.y;
@@ -916,7 +1022,7 @@ __global__ void __launch_bounds__(kWave)
                     const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < ns) {
+                        if (slot_sink(i) < ns) {
                             pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                             pp_one(s2.x, s2.y, s2.z, s2.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                         }
@@ -928,7 +1034,7 @@ __global__ void __launch_bounds__(kWave)
                     const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < ns) pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                        if (slot_sink(i) < ns) pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                 }
                 __syncthreads();
             }
@@ -954,10 +1060,18 @@ __global__ void __launch_bounds__(kWave)
                     const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < ns) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                        if (slot_sink(i) < ns)
+                            pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
                 }
             } else {
-                for (int64_t c0 = f0; c0 < f1; c0 += kWave) {
+                // A last chunk of at most 32 entries is split: both halves of
+                // the wavefront take all its entries, the lower half for the
+                // sinks in slots 0..7 and the upper half for those in 8..15,
+                // which halves its passes over the sinks.
+                const int rem = int((f1 - f0) & (kWave - 1));
+                const bool split = rem > 0 && rem <= kWave / 2 && nsink >= 2;
+                const int64_t fend = split ? f1 - rem : f1;
+                for (int64_t c0 = f0; c0 < fend; c0 += kWave) {
                     float r[kRec], cx, cy, cz;
                     load_pc(a, c0 + lane, f1, Cx, Cy, Cz, r, cx, cy, cz);
                     const float t = r[kRec - 1];
@@ -965,12 +1079,37 @@ __global__ void __launch_bounds__(kWave)
                     const int ns = sink_count(nsink);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (i < ns) pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                        if (slot_sink(i) < ns)
+                            pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
+                }
+                if (split) {
+                    constexpr int kHalf = kBucket / 2;
+                    const bool upper = lane >= kWave / 2;
+                    float r[kRec], cx, cy, cz;
+                    // entries at or past f1 (lanes beyond rem in each half) add zero
+                    load_pc(a, fend + (lane & (kWave / 2 - 1)), f1, Cx, Cy, Cz, r, cx, cy, cz);
+                    const float t = r[kRec - 1];
+                    const float eps2t = a.eps2 * t * t;
+                    const int ns = sink_count(nsink);
+#pragma unroll
+                    for (int j = 0; j < kHalf; ++j)
+                        if (slot_sink(j) < ns) {  // the slot j + 8 sink may be missing
+                            const bool hi = slot_sink(j + kHalf) < ns;
+                            const float px = upper ? sx[j + kHalf] : sx[j];
+                            const float py = upper ? sy[j + kHalf] : sy[j];
+                            const float pz = upper ? sz[j + kHalf] : sz[j];
+                            Acc4 A = upper ? acc[j + kHalf] : acc[j];
+                            pc_one(r, t, cx, cy, cz, px, py, pz, eps2t, A);
+                            if (!upper)
+                                acc[j] = A;
+                            else if (hi)
+                                acc[j + kHalf] = A;
+                        }
                 }
             }
         }
 
-        // transposing butterfly: v[4*i + c] summed over lanes -> lane 4*i + c
+        // transposing butterfly: v[4*i + c] (slot i) summed over lanes -> lane 4*i + c
         float v[4 * kBucket];
 #pragma unroll
         for (int i = 0; i < kBucket; ++i) {
@@ -989,7 +1128,7 @@ __global__ void __launch_bounds__(kWave)
                 v[k] = keep + __shfl_xor(send, o);
             }
         }
-        const int i = lane >> 2, comp = lane & 3;
+        const int i = slot_sink(lane >> 2), comp = lane & 3;
         if (i < nsink) {
             const int p = first + i;
             if (a.active == nullptr || a.active[p]) {
@@ -1004,6 +1143,7 @@ __global__ void __launch_bounds__(kWave)
                 out[p] = val;
             }
         }
+        if (lane == 0) next = queue_resolve(a.ctl, qc, next, n_top, n_items, local);
         item = __builtin_amdgcn_readfirstlane(__shfl(next, 0));
     }
     if (lane == 0 && atomicAdd(&a.ctl->waves_done, 1) == int(gridDim.x) - 1)
@@ -1036,6 +1176,9 @@ void launch_interact(int v, dim3 grid, hipStream_t stream, const RunArgs& r) {
 }
 #undef MGRAV_VARIANT
 static_assert(kNumVariants == 6, "interact_kernel and launch_interact list every variant");
+static_assert(kQueueAuto == MGRAV_QUEUE_AUTO && kQueueLpt == MGRAV_QUEUE_LPT &&
+                  kQueueLocal == MGRAV_QUEUE_LOCAL,
+              "queue orders match the header");
 
 // ---------------------------------------------------------------------
 // Ewald correction (FP64)
@@ -1582,6 +1725,7 @@ struct mgrav_ctx {
     int interact_blocks[kNumVariants] = {};  // persistent grid per variant
     int occupancy_status = 0;
     int variant = 0;  // PP + PC kernel variant in use (mgrav_autotune)
+    int queue_order = MGRAV_QUEUE_AUTO;  // work-queue layout (mgrav_set_queue_order)
     std::string err;
     bool bound = false;
     bool failed = false;
@@ -2003,6 +2147,7 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     r.parts = parts;
     int* plist = c->active ? reinterpret_cast<int*>(w + c->lay.plist) : nullptr;
     r.plist = plist;
+    r.queue_order = c->queue_order;
     L->n = p.n;
     L->n_bucket = p.n_bucket;
     L->use_mask = c->active ? 1 : 0;
@@ -2468,6 +2613,7 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
             stats->ewald_fallback = c->host_ctl->ew_fallback;
             stats->ewald_samples = int64_t(c->host_ctl->ew_samples);
             stats->ewald_sample_err = c->host_ctl->ew_err;
+            stats->queue_local = c->host_ctl->order_local;
         }
     }
     const int err = c->host_ctl->err;
@@ -2643,6 +2789,15 @@ mgrav_status mgrav_autotune(mgrav_ctx* c, float* acc, float* pot, const char* ca
         std::fprintf(f, "mgrav-autotune %s %d %d\n", key, best_v, c->direct ? 1 : 0);
         std::fclose(f);
     }
+    return MGRAV_OK;
+}
+
+mgrav_status mgrav_set_queue_order(mgrav_ctx* c, int order) {
+    if (!c) return fail(nullptr, MGRAV_ERR_INVALID_ARG, "ctx is NULL");
+    c->err.clear();
+    if (order != MGRAV_QUEUE_AUTO && order != MGRAV_QUEUE_LPT && order != MGRAV_QUEUE_LOCAL)
+        return fail(c, MGRAV_ERR_INVALID_ARG, "order must be MGRAV_QUEUE_AUTO, _LPT or _LOCAL");
+    c->queue_order = order;  // the captured launches are rebuilt when their arguments differ
     return MGRAV_OK;
 }
 

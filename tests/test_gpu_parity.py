@@ -245,6 +245,38 @@ def test_launch_modes_give_identical_results(mg_ctx):
                 assert np.all(out[1][0][act == 0] == 0) and np.all(out[1][1][act == 0] == 0)
 
 
+def test_queue_orders_give_identical_results(mg_ctx):
+    """Every layout of the work queue (cost order; locality order with the
+    costliest buckets in front and per-die segments; automatic) gives the
+    same bits, all active and with a mask, on a 3-wave variant (split last
+    PC chunk) and a prefetching 2-wave one."""
+    mg, ctx = mg_ctx
+    ps = workloads.make(3, scale_n1d=20)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    act = (np.random.default_rng(12).random(ps.n) < 0.4).astype(np.uint8)
+    info = mg.interact_variants()
+    variants = [next(v for v, t in enumerate(info) if t[1] == 3),
+                next(v for v, t in enumerate(info) if t[2])]
+    for variant in variants:
+        for mask in (None, act):
+            _case(f"queue orders, clustered_20, variant {variant}, mask={mask is not None}")
+            out = {}
+            try:
+                ctx.set_interact_variant(variant)
+                for order in (mg.QUEUE_LPT, mg.QUEUE_LOCAL, mg.QUEUE_AUTO):
+                    ctx.set_queue_order(order)
+                    a, p_, st = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t, active=mask)
+                    # automatic: cost order below 131072 active buckets
+                    assert st.queue_local == (1 if order == mg.QUEUE_LOCAL else 0)
+                    out[order] = (a, p_)
+            finally:
+                ctx.set_queue_order(mg.QUEUE_AUTO)
+                ctx.set_interact_variant(0)
+            for order in (mg.QUEUE_LOCAL, mg.QUEUE_AUTO):
+                assert np.array_equal(out[order][0], out[mg.QUEUE_LPT][0])
+                assert np.array_equal(out[order][1], out[mg.QUEUE_LPT][1])
+
+
 def test_lattice_periodic_full_size_sampled(mg_ctx):
     check_parts(mg_ctx, workloads.make(2), "lattice_64_full", sample=97)
 
