@@ -615,7 +615,9 @@ def substeps(args):
                "n_pp_interactions": st.n_pp_interactions, "n_pc_interactions": st.n_pc_interactions,
                "interactions_per_s": n_int / (ms_step * 1e-3),
                "particles_per_s": st.n_active_particles / (ms_step * 1e-3),
-               "kernel_tflops": flops / (k_ms * 1e-3) / 1e12, "ewald": ewald_row}
+               "kernel_tflops": flops / (k_ms * 1e-3) / 1e12, "ewald": ewald_row,
+               "launch": "graph" if st.graph_replay else "direct",
+               "queue_layout": "locality" if st.queue_local else "cost order"}
         rows.append(row)
         if head is None:
             head = (st, flops, k_ms, steps)
