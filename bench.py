@@ -825,6 +825,11 @@ def fmm_leg(ctx, args):
             fl_dev = {k: torch.from_numpy(getattr(fl, k)).to(dev)
                       for k in ("cc_off", "cc_src", "cc_img")}
 
+        # each list kind with the PP + PC variant that suits it best
+        ctx.bind(p, keep, ws)
+        variant, _ = ctx.autotune(acc, pot, budget_ms=1000.0)
+        res[label + "_variant"] = mg.interact_variants()[variant]
+
         def step():
             ctx.bind(p, keep, ws)
             ctx.compute(acc, pot)
@@ -856,7 +861,8 @@ def fmm_leg(ctx, args):
         f"of the two methods {diff:.2e}; host walks {t_bucket:.1f} s (tree + bucket lists), "
         f"{t_fmm_walk:.1f} s (fmm lists)")
     return {"workload": f"{cfg.name} (n={ps.n}, theta {cfg.theta}, exact Ewald)",
-            "bucket_walk": res["bucket"], "fmm": res["fmm"],
+            "bucket_walk": dict(res["bucket"], pp_pc_variant=res["bucket_variant"]),
+            "fmm": dict(res["fmm"], pp_pc_variant=res["fmm_variant"]),
             "rms_rel_difference_fmm_vs_bucket_walk": diff,
             "host_seconds_tree_and_bucket_lists": t_bucket,
             "host_seconds_fmm_lists": t_fmm_walk}
