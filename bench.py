@@ -782,6 +782,7 @@ def substeps(args):
                                                   st.n_pc_interactions)
     if not args.no_fmm:
         out["fmm"] = fmm_leg(ctx, args)
+        ctx.set_interact_variant(tuned["index"])  # the 512^3 set's choice again
     if not args.no_kdk:
         del tensors, prob, ws, lists, tree
         torch.cuda.empty_cache()
