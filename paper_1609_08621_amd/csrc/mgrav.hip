@@ -153,7 +153,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Workspace segments (byte offsets from the workspace base).
 struct Layout {
     size_t ctl, pdat, work, items, bins, cellrec, ppent, ewald, ewsample, cinfo, plist, ewbuf,
-        total;
+        need, total;
 };
 
 // Per cell, written first by the staging: the bounding-box centre and, for
@@ -199,6 +199,8 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     o += align256(sizeof(int) * n);
     l.ewbuf = o;
     o += align256(sizeof(double) * 4 * n);
+    l.need = o;  // two flags per cell for the staging of a masked compute
+    o += align256(2 * size_t(n_cell));
     l.total = o;
     return l;
 }
@@ -252,13 +254,37 @@ struct StageArgs {
     const uint8_t* __restrict__ pp_img;
     const uint8_t* __restrict__ pp_sub;  // nullable: 0 whole leaf, k + 1 its k-th particle
     const int64_t* __restrict__ pc_off;
+    const int32_t* __restrict__ pc_src;
     Control* ctl;
     float4* pdat;
     BucketWork* work;
     float* cellrec;
     float4* ppent;
     CellInfo* cinfo;
+    // Staging for a masked compute (active set): only what the active
+    // buckets read.  need_rec[c]: cell c is a PC source of an active bucket
+    // (its record); need_src[c]: leaf c is a PP source or the sink of an
+    // active bucket (its particles and CellInfo).  NULL: stage everything.
+    const uint8_t* __restrict__ active;
+    uint8_t* need_rec;
+    uint8_t* need_src;
 };
+
+// The bounding-box centre and, for a valid bucket (a leaf with 1..16
+// particles inside [0, n)), the particle range of cell c (count 0 otherwise).
+__device__ __forceinline__ CellInfo cell_info(const StageArgs& a, int64_t c) {
+    const double* bb = a.bbox + 6 * c;
+    CellInfo ci;
+    ci.cx = 0.5 * (bb[0] + bb[3]);
+    ci.cy = 0.5 * (bb[1] + bb[4]);
+    ci.cz = 0.5 * (bb[2] + bb[5]);
+    const int64_t f = a.cell_first[c];
+    const int k = a.cell_count[c];
+    const bool ok = a.child[2 * c] < 0 && k >= 1 && k <= kBucket && f >= 0 && f + k <= a.n;
+    ci.first = ok ? int(f) : 0;
+    ci.count = ok ? k : 0;
+    return ci;
+}
 
 // The control block (counters, error bits) into pinned host memory: the
 // last kernel of a compute; the host reads it after the completion event.
@@ -310,19 +336,8 @@ __global__ void k_stage_cells(StageArgs a) {
     }
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= a.n_cell) return;
-    {
-        const double* bb = a.bbox + 6 * c;
-        CellInfo ci;
-        ci.cx = 0.5 * (bb[0] + bb[3]);
-        ci.cy = 0.5 * (bb[1] + bb[4]);
-        ci.cz = 0.5 * (bb[2] + bb[5]);
-        const int64_t f = a.cell_first[c];
-        const int k = a.cell_count[c];
-        const bool ok = a.child[2 * c] < 0 && k >= 1 && k <= kBucket && f >= 0 && f + k <= a.n;
-        ci.first = ok ? int(f) : 0;
-        ci.count = ok ? k : 0;
-        a.cinfo[c] = ci;
-    }
+    if (!a.active || a.need_src[c]) a.cinfo[c] = cell_info(a, c);
+    if (a.active && !a.need_rec[c]) return;
     const double* m = a.mom + 32 * c;
     double r[kRec];
     r[0] = m[0];
@@ -375,17 +390,64 @@ __device__ inline int group_sum(int v) {
     for (int o = kStageLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
+// Staging for a masked compute: clear the two flag arrays (a fill kernel,
+// so that the staging can be captured in a graph), then mark what the
+// active buckets read: their own leaves and PP source leaves (particles,
+// CellInfo) and their PC source cells (records).  Plain stores of 1: every
+// writer stores the same value.  Entries outside their arrays are skipped
+// here and reported by the staging.
+__global__ void __launch_bounds__(256) k_need_clear(StageArgs a) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(a.need_rec);  // need_src follows need_rec
+    const int64_t words = (2 * a.n_cell + 3) / 4;           // within the padded segment
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
+         i += int64_t(gridDim.x) * blockDim.x)
+        w[i] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_need_mark(StageArgs a) {
+    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStageLanes;
+    const int sl = int(threadIdx.x % kStageLanes);
+    if (b >= a.n_bucket) return;  // whole groups
+    const int64_t s = a.bucket_cell[b];
+    if (s < 0 || s >= a.n_cell) return;
+    const CellInfo ci = cell_info(a, s);
+    const bool act = group_or(sl < ci.count && a.active[ci.first + sl] ? 1 : 0) != 0;
+    if (!act) return;
+    if (sl == 0) a.need_src[s] = 1;
+    const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
+    if (e0 >= 0 && e0 <= e1 && e1 <= a.n_pp)
+        for (int64_t e = e0 + sl; e < e1; e += kStageLanes) {
+            const int32_t src = a.pp_src[e];
+            if (src >= 0 && src < a.n_cell) a.need_src[src] = 1;
+        }
+    const int64_t g0 = a.pc_off[b], g1 = a.pc_off[b + 1];
+    if (g0 >= 0 && g0 <= g1 && g1 <= a.n_pc)
+        for (int64_t e = g0 + sl; e < g1; e += kStageLanes) {
+            const int32_t src = a.pc_src[e];
+            if (src >= 0 && src < a.n_cell) a.need_rec[src] = 1;
+        }
+}
+
 __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
     const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStageLanes;
     const int sl = int(threadIdx.x % kStageLanes);
     if (b >= a.n_bucket) return;  // whole groups: the first n_bucket groups are in range
     const int64_t s = a.bucket_cell[b];
     const bool sink_ok = s >= 0 && s < a.n_cell;
-    const CellInfo ci = sink_ok ? a.cinfo[s] : CellInfo{0.0, 0.0, 0.0, 0, 0};
+    // (for a masked compute the CellInfo of inactive sinks is not staged)
+    const CellInfo ci = !sink_ok ? CellInfo{0.0, 0.0, 0.0, 0, 0}
+                                 : (a.active ? cell_info(a, s) : a.cinfo[s]);
+    // with a mask: whether any sink is active (only then are the bucket's
+    // lists staged), and whether its particles are read at all
+    bool act = true, stage_sinks = true;
+    if (a.active) {
+        act = group_or(sl < ci.count && a.active[ci.first + sl] ? 1 : 0) != 0;
+        stage_sinks = sink_ok && a.need_src[s];
+    }
     // the sink particles
     if (ci.count == 0) {
         if (sl == 0) atomicOr(&a.ctl->err, kErrTree);
-    } else if (sl < ci.count) {
+    } else if (sl < ci.count && stage_sinks) {
         const int64_t p = ci.first + sl;
         double x, y, z;
         load_pos(a.pin, p, x, y, z);
@@ -394,8 +456,8 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
             atomicOr(&a.ctl->err, kErrParticle);
         a.pdat[p] = make_float4(float(x - ci.cx), float(y - ci.cy), float(z - ci.cz), float(m));
     }
-    // the PP entries
-    const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
+    // the PP entries (of an active bucket only, with a mask)
+    const int64_t e0 = act ? a.pp_off[b] : 0, e1 = act ? a.pp_off[b + 1] : 0;
     const bool range_ok = e0 >= 0 && e0 <= e1 && e1 <= a.n_pp;
     int nsrc = 0, self = 0, bad = 0;
     if (!range_ok || !sink_ok) bad = 1;
@@ -437,7 +499,7 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
             }
         }
     }
-    const int64_t g0 = a.pc_off[b], g1 = a.pc_off[b + 1];
+    const int64_t g0 = act ? a.pc_off[b] : 0, g1 = act ? a.pc_off[b + 1] : 0;
     const bool pc_ok = g0 >= 0 && g0 <= g1 && g1 <= a.n_pc;
     if (!pc_ok) bad = 1;
     bad = group_or(bad);
@@ -1751,6 +1813,7 @@ struct mgrav_ctx {
     } gs[2];
     int last_set = -1;            // graph set of the last compute
     bool stage_pending = false;   // bound, staging kernels not yet enqueued
+    bool stage_partial = false;   // the last staging covered a mask's needs only
     bool no_graph = false;        // capture failed once: launch directly
     int graph_error = 0;          // the HIP error that made it fail
     bool direct = false;          // MGRAV_LAUNCH_DIRECT chosen: no graphs
@@ -1867,6 +1930,7 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.pp_img = p.pp_img;
     a.pp_sub = p.pp_sub;
     a.pc_off = p.pc_off;
+    a.pc_src = p.pc_src;
     char* w = c->ws;
     a.ctl = reinterpret_cast<Control*>(w + c->lay.ctl);
     a.pdat = reinterpret_cast<float4*>(w + c->lay.pdat);
@@ -1874,6 +1938,9 @@ StageArgs stage_args(mgrav_ctx* c) {
     a.cellrec = reinterpret_cast<float*>(w + c->lay.cellrec);
     a.ppent = reinterpret_cast<float4*>(w + c->lay.ppent);
     a.cinfo = reinterpret_cast<CellInfo*>(w + c->lay.cinfo);
+    a.active = nullptr;  // everything; make_launch sets the mask for a masked compute
+    a.need_rec = reinterpret_cast<uint8_t*>(w + c->lay.need);
+    a.need_src = a.need_rec + p.n_cell;
     return a;
 }
 
@@ -2038,6 +2105,7 @@ mgrav_status mgrav_bind(mgrav_ctx* c, const mgrav_problem* p, void* workspace, s
     // the staging kernels run at the start of the next compute (inside its
     // first graph) or, if a wait comes first, at that wait
     c->stage_pending = true;
+    c->stage_partial = false;
     c->bound = true;
     return MGRAV_OK;
 }
@@ -2121,7 +2189,12 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
     std::memset(L, 0, sizeof(*L));  // padding too: the struct is compared byte-wise
     const mgrav_problem& p = c->prob;
     L->stage = c->stage_pending ? 1 : 0;
-    if (L->stage) L->s = stage_args(c);
+    if (L->stage) {
+        L->s = stage_args(c);
+        // with a mask, stage only what the active buckets read; the staging
+        // then stays pending for the next compute
+        L->s.active = c->active;
+    }
     L->host_ctl = c->host_ctl;
     char* w = c->ws;
     RunArgs& r = L->r;
@@ -2244,9 +2317,16 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
 
 // The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
 static void enqueue_stage(hipStream_t st, const StageArgs& a) {
+    const int64_t nb = a.n_bucket * kStageLanes;
+    if (a.active) {
+        const int64_t words = (2 * a.n_cell + 3) / 4;
+        const int64_t gb = (words + 255) / 256;
+        hipLaunchKernelGGL(k_need_clear, dim3(unsigned(gb < 1024 ? gb : 1024)), dim3(256), 0, st,
+                           a);
+        hipLaunchKernelGGL(k_need_mark, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, a);
+    }
     hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0, st,
                        a);
-    const int64_t nb = a.n_bucket * kStageLanes;
     hipLaunchKernelGGL(k_stage_bucket, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, a);
 }
 
@@ -2516,7 +2596,8 @@ mgrav_status mgrav_compute_parts(mgrav_ctx* c, int parts, float* acc, float* pot
     // counters and error bits travel back with the work: the last kernel of
     // phase 2 copies the control block into pinned host memory
     c->have_run = true;
-    c->stage_pending = false;
+    c->stage_pending = L.stage && L.s.active != nullptr;
+    c->stage_partial = c->stage_pending;
     c->last_set = L.stage;
     return MGRAV_OK;
 }
@@ -2546,7 +2627,7 @@ mgrav_status mgrav_wait(mgrav_ctx* c, double timeout_s, mgrav_stats* stats) {
     c->err.clear();
     if (!c->bound) return fail(c, MGRAV_ERR_STATE, "wait before bind");
     HIP_TRY(c, hipSetDevice(c->device));
-    if (c->stage_pending) {  // bind without compute: stage now, for its checks
+    if (c->stage_pending && !c->stage_partial) {  // bind without compute: stage now, for its checks
         const StageArgs a = stage_args(c);
         enqueue_stage(c->stream, a);
         hipLaunchKernelGGL(k_copy_control, dim3(1), dim3(kWave), 0, c->stream, a.ctl,

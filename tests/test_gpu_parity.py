@@ -335,7 +335,31 @@ def test_active_subsets_full_size(mg_ctx):
         assert st.n_active_particles == on.sum()
         assert np.array_equal(a[on], a_full[on]) and np.array_equal(pa[on], p_full[on])
         assert np.all(a[~on] == -3.0) and np.all(pa[~on] == -3.0)
+    # a bind before each masked compute: the staging then covers only what
+    # the active buckets read (their particles and lists, the PP source
+    # particles and the PC source cells) and stays pending
+    for frac in (0.1, 0.01, 0.5):
+        _case(f"clustered_128_full bind + {frac:.0%} active (masked staging)")
+        active = workloads.active_by_acceleration(np.linalg.norm(a_full, axis=1), frac)
+        acc2 = torch.full((3 * ps.n,), -5.0, dtype=torch.float32, device=dev)
+        pot2 = torch.full((ps.n,), -5.0, dtype=torch.float32, device=dev)
+        ctx.bind(p, tensors)
+        ctx.set_active(torch.from_numpy(active).to(dev))
+        for _ in range(2):  # the second compute stages again (still pending)
+            ctx.compute(acc2, pot2)
+            st = ctx.wait(120)
+        a = acc2.cpu().numpy().reshape(3, -1).T
+        pa = pot2.cpu().numpy()
+        on = active.astype(bool)
+        print(f"  {frac:.0%}: ms={st.ms_total:.3f}", flush=True)
+        assert np.array_equal(a[on], a_full[on]) and np.array_equal(pa[on], p_full[on])
+        assert np.all(a[~on] == -5.0) and np.all(pa[~on] == -5.0)
     ctx.set_active(None)
+    # and a full compute after a masked one stages everything again
+    ctx.compute(acc, pot)
+    ctx.wait(120)
+    assert np.array_equal(acc.cpu().numpy().reshape(3, -1).T, a_full)
+    assert np.array_equal(pot.cpu().numpy(), p_full)
 
 
 def test_unperturbed_lattice_cancellation(mg_ctx):
