@@ -429,9 +429,10 @@ typedef struct {
 /* Device workspace the caller must provide to mgrav_bind for `p`:
  * 16 bytes per particle (staged offsets and masses) + 4 (active list)
  * + 32 (Ewald correction buffered beside the PP + PC kernel),
- * 176 + 32 bytes per cell (PC records, cell centres and ranges), 16 per
- * PP entry, 53 per bucket (work descriptor, queue, cost bin) and about
- * 1.6 MB of fixed tables, each segment aligned to 256 bytes. */
+ * 176 + 32 + 2 bytes per cell (PC records, cell centres and ranges, two
+ * flags of the masked staging), 16 per PP entry, 53 per bucket (work
+ * descriptor, queue, cost bin) and about 1.6 MB of fixed tables, each
+ * segment aligned to 256 bytes. */
 mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
 
 /* Bind a problem: checks the scalar arguments on the host and arranges
@@ -453,8 +454,14 @@ mgrav_status mgrav_workspace_size(const mgrav_problem *p, size_t *bytes);
  * mgrav_workspace_size() bytes, 256-byte aligned, owned by the caller and
  * borrowed until the next bind or destroy.  The device reads the positions
  * and lists when the staging runs, so binding once per step with moved
- * positions (same buffers) re-stages them.  Re-binding is allowed at any
- * time after the previous work on the stream. */
+ * positions (same buffers) re-stages them.  When the compute that stages
+ * has a mask (mgrav_set_active), only what its active buckets read is
+ * staged (their particles, PP entries and work, the particles of their PP
+ * source leaves, the records of their PC source cells; every bucket's work
+ * descriptor) and the staging stays pending: the next compute stages again
+ * for its own mask, or everything without one.  Results do not depend on
+ * which staging ran.  Re-binding is allowed at any time after the previous
+ * work on the stream. */
 mgrav_status mgrav_bind(mgrav_ctx *ctx, const mgrav_problem *p, void *workspace, size_t bytes);
 
 /* Size of the library's static workspace (64 MiB; one copy per GPU). */
