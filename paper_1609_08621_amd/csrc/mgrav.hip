@@ -941,12 +941,19 @@ __device__ int queue_resolve(Control* ctl, QueueCursor& q, int raw, int n_top, i
     }
 }
 
-// Register slot s of a work item's sinks holds sink slot_sink(s): the even
-// sinks fill slots 0..7 and the odd ones slots 8..15, so that the sinks of
-// any bucket split evenly between the two halves of the slot range (the
-// split last PC chunk below gives each half of the wavefront one half).
-__device__ __forceinline__ constexpr int slot_sink(int s) {
-    return s < kBucket / 2 ? 2 * s : 2 * (s - kBucket / 2) + 1;
+// Register slots of a work item's sinks: the active sinks of even index
+// fill slots 0..7 in order and those of odd index slots 8..15, so that the
+// sinks of a bucket split evenly between the two halves of the slot range
+// (the split last PC chunk below gives each half of the wavefront one
+// half), only active sinks are evaluated, and a sink's half (its index's
+// parity) is the same with or without a mask: its sums then see the same
+// operations in the same lanes, so a masked compute gives the bits of the
+// full one.  mask: bit k = sink k is active (bit 0 of each pair even).
+__device__ __forceinline__ int slot_rank_bit(uint32_t m, int r) {
+    // index of the r-th (from 0) set bit of m, 16 if there is none
+    for (int t = 0; t < kBucket / 2 - 1; ++t)
+        if (t < r) m &= m - 1u;
+    return m ? __builtin_ctz(m) : kBucket;
 }
 
 // Persistent PP + PC kernel.  One wavefront per work item (a sink bucket
@@ -1010,15 +1017,30 @@ __global__ void __launch_bounds__(kWave)
         // prefetch's 44 more with 2) read them through the constant address
         // space as scalar loads into scalar registers.
         constexpr bool kSinksInVgprs = kWaves == 2 && !kPrefetch;
+        constexpr int kHalf = kBucket / 2;
+        uint32_t me, mo;  // active sinks of even and of odd index
+        {
+            const bool on = lane < nsink && (a.active == nullptr || a.active[first + lane]);
+            const uint32_t m = uint32_t(__ballot(on)) & 0xFFFFu;
+            me = __builtin_amdgcn_readfirstlane(m & 0x5555u);
+            mo = __builtin_amdgcn_readfirstlane(m & 0xAAAAu);
+        }
+        const int n_even = __builtin_popcount(me), n_odd = __builtin_popcount(mo);
+        const int k_any = __builtin_ctz(me | mo | 0x10000u);  // a sink for the empty slots
         float sx[kBucket], sy[kBucket], sz[kBucket];
+        {
+            uint32_t re = me, ro = mo;
 #pragma unroll
-        for (int i = 0; i < kBucket; ++i) {
-            const int k = slot_sink(i);
-            const int p = first + (k < nsink ? k : nsink - 1);
-            const float4 q = kSinksInVgprs ? a.pdat[p] : load_uniform(a.pdat, p);
-            sx[i] = q.x;
-            sy[i] = q.y;
-            sz[i] = q.z;
+            for (int i = 0; i < kBucket; ++i) {
+                uint32_t& r = i < kHalf ? re : ro;
+                const int k = r ? __builtin_ctz(r) : k_any;
+                r &= r - 1u;
+                const int p = first + (k < nsink ? k : 0);
+                const float4 q = kSinksInVgprs ? a.pdat[p] : load_uniform(a.pdat, p);
+                sx[i] = q.x;
+                sy[i] = q.y;
+                sz[i] = q.z;
+            }
         }
         Acc4 acc[kBucket];
 #pragma unroll
@@ -1081,10 +1103,10 @@ __global__ void __launch_bounds__(kWave)
                 for (; t0 + 2 * kWave <= total; t0 += 2 * kWave) {
                     const float4 s = lds[t0 + lane];
                     const float4 s2 = lds[t0 + kWave + lane];
-                    const int ns = sink_count(nsink);
+                    const int ne = sink_count(n_even), no = sink_count(n_odd);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (slot_sink(i) < ns) {
+                        if (i < kHalf ? i < ne : i - kHalf < no) {
                             pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                             pp_one(s2.x, s2.y, s2.z, s2.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                         }
@@ -1093,10 +1115,11 @@ __global__ void __launch_bounds__(kWave)
                     const int t = t0 + lane;
                     // padding lanes: a massless source at the bucket centre (finite, adds 0)
                     const float4 s = t < total ? lds[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    const int ns = sink_count(nsink);
+                    const int ne = sink_count(n_even), no = sink_count(n_odd);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (slot_sink(i) < ns) pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
+                        if (i < kHalf ? i < ne : i - kHalf < no)
+                            pp_one(s.x, s.y, s.z, s.w, sx[i], sy[i], sz[i], a.eps2, acc[i]);
                 }
                 __syncthreads();
             }
@@ -1119,10 +1142,10 @@ __global__ void __launch_bounds__(kWave)
                         load_pc(a, c0 + kWave + lane, f1, Cx, Cy, Cz, rn, nx, ny, nz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
-                    const int ns = sink_count(nsink);
+                    const int ne = sink_count(n_even), no = sink_count(n_odd);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (slot_sink(i) < ns)
+                        if (i < kHalf ? i < ne : i - kHalf < no)
                             pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
                 }
             } else {
@@ -1140,34 +1163,34 @@ __global__ void __launch_bounds__(kWave)
                     load_pc(a, c0 + lane, f1, Cx, Cy, Cz, r, cx, cy, cz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
-                    const int ns = sink_count(nsink);
+                    const int ne = sink_count(n_even), no = sink_count(n_odd);
 #pragma unroll
                     for (int i = 0; i < kBucket; ++i)
-                        if (slot_sink(i) < ns)
+                        if (i < kHalf ? i < ne : i - kHalf < no)
                             pc_one(r, t, cx, cy, cz, sx[i], sy[i], sz[i], eps2t, acc[i]);
                 }
                 if constexpr (kSplitTail) if (split) {
-                    constexpr int kHalf = kBucket / 2;
                     const bool upper = lane >= kWave / 2;
                     float r[kRec], cx, cy, cz;
                     // entries at or past f1 (lanes beyond rem in each half) add zero
                     load_pc(a, fend + (lane & (kWave / 2 - 1)), f1, Cx, Cy, Cz, r, cx, cy, cz);
                     const float t = r[kRec - 1];
                     const float eps2t = a.eps2 * t * t;
-                    const int ns = sink_count(nsink);
+                    const int ne = sink_count(n_even), no = sink_count(n_odd);
 #pragma unroll
                     for (int j = 0; j < kHalf; ++j)
-                        if (slot_sink(j) < ns) {  // the slot j + 8 sink may be missing
-                            const bool hi = slot_sink(j + kHalf) < ns;
+                        if (j < ne || j < no) {  // either slot j or j + 8 may be empty
+                            const bool lo = j < ne, hi = j < no;
                             const float px = upper ? sx[j + kHalf] : sx[j];
                             const float py = upper ? sy[j + kHalf] : sy[j];
                             const float pz = upper ? sz[j + kHalf] : sz[j];
                             Acc4 A = upper ? acc[j + kHalf] : acc[j];
                             pc_one(r, t, cx, cy, cz, px, py, pz, eps2t, A);
-                            if (!upper)
-                                acc[j] = A;
-                            else if (hi)
+                            if (!upper) {
+                                if (lo) acc[j] = A;
+                            } else if (hi) {
                                 acc[j + kHalf] = A;
+                            }
                         }
                 }
             }
@@ -1192,10 +1215,11 @@ __global__ void __launch_bounds__(kWave)
                 v[k] = keep + __shfl_xor(send, o);
             }
         }
-        const int i = slot_sink(lane >> 2), comp = lane & 3;
-        if (i < nsink) {
+        const int slot = lane >> 2, comp = lane & 3;
+        const int i = slot_rank_bit(slot < kHalf ? me : mo, slot & (kHalf - 1));
+        if (i < nsink) {  // an active sink (16: an empty slot)
             const int p = first + i;
-            if (a.active == nullptr || a.active[p]) {
+            {
                 float val = v[0];
                 if (comp == 3 && (a.parts & MGRAV_PART_PP) && wk.self) {
                     // remove the self pair, which entered as -m_i / eps
