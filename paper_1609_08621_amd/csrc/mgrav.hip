@@ -63,6 +63,7 @@ constexpr int kVariantWaves[kNumVariants] = {3, 3, 2, 2, 2, 2};
 constexpr bool kVariantPrefetch[kNumVariants] = {false, false, false, false, true, true};
 constexpr int kMaxH2 = 64;                 // largest k-space cut-off |h|^2
 constexpr int kMaxHalfK = 1054;            // half-space wave vectors with |h|^2 <= 64
+constexpr int kEwCoefSlots = 128;          // Ewald radial constants after the k-space rows
 constexpr int kErrTree = 1, kErrList = 2, kErrParticle = 4;
 
 // Control block at the start of the workspace.
@@ -190,7 +191,7 @@ Layout make_layout(int64_t n, int64_t n_cell, int64_t n_bucket, int64_t n_pp, in
     l.ppent = o;
     o += align256(sizeof(float4) * (n_pp > 0 ? n_pp : 1));
     l.ewald = o;
-    o += align256(sizeof(double) * (64 + 8 * kMaxHalfK));
+    o += align256(sizeof(double) * (64 + 8 * kMaxHalfK + kEwCoefSlots));
     l.ewsample = o;
     o += align256(sizeof(double) * kSampleRec * kMaxEwaldSamples);
     l.cinfo = o;
@@ -1313,6 +1314,42 @@ __constant__ int c_ax4[15][4] = {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0
                                  {0, 1, 2, 2}, {0, 2, 2, 2}, {1, 1, 1, 1}, {1, 1, 1, 2},
                                  {1, 1, 2, 2}, {1, 2, 2, 2}, {2, 2, 2, 2}};
 
+#include "erfcx_poly.inc"
+
+// 1/(2j + 11) and 1/(j + 1) for the power series, 1/(2n + 1) for the
+// downward recurrence: constants, so the loops below divide nothing.
+struct EwaldConsts {
+    double inv_odd[30];   // 1 / (2j + 11)
+    double inv_next[30];  // 1 / (j + 1)
+    double inv_2n1[6];    // 1 / (2n + 1)
+};
+__constant__ EwaldConsts c_ew = {
+    {1.0 / 11, 1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21, 1.0 / 23, 1.0 / 25, 1.0 / 27,
+     1.0 / 29, 1.0 / 31, 1.0 / 33, 1.0 / 35, 1.0 / 37, 1.0 / 39, 1.0 / 41, 1.0 / 43, 1.0 / 45,
+     1.0 / 47, 1.0 / 49, 1.0 / 51, 1.0 / 53, 1.0 / 55, 1.0 / 57, 1.0 / 59, 1.0 / 61, 1.0 / 63,
+     1.0 / 65, 1.0 / 67, 1.0 / 69},
+    {1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,
+     1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18,
+     1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
+     1.0 / 28, 1.0 / 29, 1.0 / 30},
+    {1.0 / 1, 1.0 / 3, 1.0 / 5, 1.0 / 7, 1.0 / 9, 1.0 / 11}};
+
+// Constants of the radial functions, written by k_ewald_setup after the
+// k-space rows and read per image through scalar loads (kept in memory so
+// that they do not occupy vector registers across the image loop).
+constexpr int kEwCoef = 64 + 8 * kMaxHalfK;
+constexpr int kEwInvOdd = 0;      // 1 / (2j + 11), j < 30
+constexpr int kEwInvNext = 30;    // 1 / (j + 1), j < 30
+constexpr int kEwInv2n1 = 60;     // 1 / (2n + 1), n < 6
+constexpr int kEwErfcx = 66;      // erfcx polynomial, kErfcxDeg + 1 values
+constexpr int kEwK = 66 + 19;     // k_m = (-2 alpha^2)^m / (alpha sqrt(pi)), m < 6
+constexpr int kEwG5 = kEwK + 6;   // 2 alpha / sqrt(pi) (-32 alpha^10)
+constexpr int kEwAl2 = kEwG5 + 1; // alpha^2
+constexpr int kEwTs = kEwAl2 + 1; // (2 / alpha) kErfcxScale
+constexpr int kEwCoefCount = kEwTs + 1;
+static_assert(kErfcxDeg + 1 == 19, "erfcx block size");
+static_assert(kEwCoefCount <= kEwCoefSlots, "radial constants overflow their block");
+
 // Root coefficients in unit-box scaling (order k scaled by L^-k), masked
 // by the requested order, and the k-space table for the half space of
 // wave vectors (each row stands for h and -h).  One block: the candidate
@@ -1417,56 +1454,61 @@ __global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
         nk += chunk;
     }
     if (threadIdx.x == 0) a.table[44] = double(nk < kMaxHalfK ? nk : kMaxHalfK);
+    // constants of the radial functions
+    double* cf = a.table + kEwCoef;
+    const int t = threadIdx.x;
+    if (t < 30) {
+        cf[kEwInvOdd + t] = c_ew.inv_odd[t];
+        cf[kEwInvNext + t] = c_ew.inv_next[t];
+    }
+    if (t < 6) cf[kEwInv2n1 + t] = c_ew.inv_2n1[t];
+    if (t <= kErfcxDeg) cf[kEwErfcx + t] = c_erfcx[t];
+    if (t == 0) {
+        const double SQRT_PI = 1.77245385090551602729;
+        const double al = a.alpha, al2 = al * al;
+        double k = 1.0 / (al * SQRT_PI);
+        cf[kEwK] = k;
+        for (int m = 1; m < 6; ++m) {
+            k = k * (-2.0 * al2);
+            cf[kEwK + m] = k;
+        }
+        cf[kEwG5] = 2.0 * al / SQRT_PI * (-32.0 * al2 * al2 * al2 * al2 * al2);
+        cf[kEwAl2] = al2;
+        cf[kEwTs] = (2.0 / al) * kErfcxScale;
+    }
 }
 
-#include "erfcx_poly.inc"
 
-// 1/(2j + 11) and 1/(j + 1) for the power series, 1/(2n + 1) for the
-// downward recurrence: constants, so the loops below divide nothing.
-struct EwaldConsts {
-    double inv_odd[30];   // 1 / (2j + 11)
-    double inv_next[30];  // 1 / (j + 1)
-    double inv_2n1[6];    // 1 / (2n + 1)
+struct TableRec {
+    const double* t;
+    __device__ double operator[](int i) const { return load_uniform(t, i); }
 };
-__constant__ EwaldConsts c_ew = {
-    {1.0 / 11, 1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21, 1.0 / 23, 1.0 / 25, 1.0 / 27,
-     1.0 / 29, 1.0 / 31, 1.0 / 33, 1.0 / 35, 1.0 / 37, 1.0 / 39, 1.0 / 41, 1.0 / 43, 1.0 / 45,
-     1.0 / 47, 1.0 / 49, 1.0 / 51, 1.0 / 53, 1.0 / 55, 1.0 / 57, 1.0 / 59, 1.0 / 61, 1.0 / 63,
-     1.0 / 65, 1.0 / 67, 1.0 / 69},
-    {1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,
-     1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18,
-     1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
-     1.0 / 28, 1.0 / 29, 1.0 / 30},
-    {1.0 / 1, 1.0 / 3, 1.0 / 5, 1.0 / 7, 1.0 / 9, 1.0 / 11}};
 
-// Radial derivatives g_n = ((1/r) d/dr)^n of erf(alpha r)/r (near images)
-// or of -erfc(alpha r)/r (outer real-space shells), n = 0..5, unit box.
-// Near images with alpha r < sqrt(2): g_5 from its power series
+
+// Radial derivatives g_n = ((1/r) d/dr)^n of erf(alpha r)/r, n = 0..5, for
+// the near images (|n_a| <= 1), unit box.  With alpha r < sqrt(2): g_5 from
+// its power series
 //   g_5 = (2 alpha/sqrt(pi)) (-2 alpha^2)^5 sum_j (-x)^j / (j! (2j + 11)),
 //   x = alpha^2 r^2,
 // the rest by the downward recurrence g_n = -(r^2 g_{n+1} + k_{n+1} e^{-x})
 // / (2n+1) with k_m = (-2 alpha^2)^m / (alpha sqrt(pi)); otherwise upward
-// from the closed form (the same recurrence solved for g_{n+1}).
-// E = exp(-alpha^2 r^2) is passed in (k_ewald builds it from per-axis
-// factors for the near images).
-__device__ void ewald_radial_e(double r2, double alpha, bool near, double E, double g[6]) {
-    const double SQRT_PI = 1.77245385090551602729;
-    const double al2 = alpha * alpha;
-    const double x = al2 * r2;
-    double k[6];
-    k[0] = 1.0 / (alpha * SQRT_PI);
-#pragma unroll
-    for (int m = 1; m < 6; ++m) k[m] = k[m - 1] * (-2.0 * al2);
-    if (near && x < 2.0) {
+// from the closed form (the same recurrence solved for g_{n+1}), with
+// erf(z) = 1 - e^{-z^2} erfcx(z), erfcx from its polynomial in 2/z.
+// E = exp(-alpha^2 r^2) is passed in (built from per-axis factors).
+template <typename C>
+__device__ __forceinline__ void ewald_radial_near(const C& c, double r2, double E, double g[6]) {
+    const double x = c[kEwAl2] * r2;
+    if (x < 2.0) {
         double sum = 0.0, term = 1.0;
 #pragma unroll
         for (int j = 0; j < 30; ++j) {
-            sum = fma(term, c_ew.inv_odd[j], sum);
-            term *= -x * c_ew.inv_next[j];
+            sum = fma(term, c[kEwInvOdd + j], sum);
+            term *= -x * c[kEwInvNext + j];
         }
-        g[5] = 2.0 * alpha / SQRT_PI * (-32.0 * al2 * al2 * al2 * al2 * al2) * sum;
+        g[5] = c[kEwG5] * sum;
 #pragma unroll
-        for (int n = 4; n >= 0; --n) g[n] = -(r2 * g[n + 1] + k[n + 1] * E) * c_ew.inv_2n1[n];
+        for (int n = 4; n >= 0; --n)
+            g[n] = -(r2 * g[n + 1] + c[kEwK + n + 1] * E) * c[kEwInv2n1 + n];
         return;
     }
     // 1/r from the hardware reciprocal square root refined by two Newton
@@ -1475,48 +1517,143 @@ __device__ void ewald_radial_e(double r2, double alpha, bool near, double E, dou
     inv_r = inv_r * fma(-0.5 * r2, inv_r * inv_r, 1.5);
     inv_r = inv_r * fma(-0.5 * r2, inv_r * inv_r, 1.5);
     const double inv_r2 = inv_r * inv_r;
-    if (near) {
-        // erf(z) = 1 - e^{-z^2} erfcx(z) for z = alpha r >= sqrt(2), with the
-        // exponential already at hand and erfcx from its polynomial in 2/z;
-        // beyond z = 6.5, e^{-z^2} erfcx(z) < 1e-19 and erf(z) = 1 in double
-        double er = 1.0;
-        if (x < 42.25) {  // z < 6.5
-            const double t = fma((2.0 / alpha) * kErfcxScale, inv_r, kErfcxShift);
-            double h = c_erfcx[kErfcxDeg];
+    // beyond z = 6.5, e^{-z^2} erfcx(z) < 1e-19 and erf(z) = 1 in double
+    double er = 1.0;
+    if (x < 42.25) {  // z < 6.5
+        const double t = fma(c[kEwTs], inv_r, kErfcxShift);
+        double h = c[kEwErfcx + kErfcxDeg];
 #pragma unroll
-            for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, c_erfcx[k]);
-            er = fma(-E, h, 1.0);
-        }
-        g[0] = er * inv_r;
+        for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, c[kEwErfcx + k]);
+        er = fma(-E, h, 1.0);
+    }
+    g[0] = er * inv_r;
 #pragma unroll
-        for (int n = 0; n < 5; ++n) g[n + 1] = -(double(2 * n + 1) * g[n] + k[n + 1] * E) * inv_r2;
-    } else {
-        double e = erfc(alpha * r2 * inv_r) * inv_r;
-        g[0] = -e;
+    for (int n = 0; n < 5; ++n)
+        g[n + 1] = -(double(2 * n + 1) * g[n] + c[kEwK + n + 1] * E) * inv_r2;
+}
+
+// The same for the outer real-space shells, of -erfc(alpha r)/r.
+template <typename C>
+__device__ void ewald_radial_far(const C& c, double r2, double alpha, double g[6]) {
+    const double E = exp(-c[kEwAl2] * r2);
+    double inv_r = __builtin_amdgcn_rsq(r2);
+    inv_r = inv_r * fma(-0.5 * r2, inv_r * inv_r, 1.5);
+    inv_r = inv_r * fma(-0.5 * r2, inv_r * inv_r, 1.5);
+    const double inv_r2 = inv_r * inv_r;
+    double e = erfc(alpha * r2 * inv_r) * inv_r;
+    g[0] = -e;
 #pragma unroll
-        for (int n = 0; n < 5; ++n) {
-            e = (k[n + 1] * E - double(2 * n + 1) * e) * inv_r2;
-            g[n + 1] = -e;
-        }
+    for (int n = 0; n < 5; ++n) {
+        e = (c[kEwK + n + 1] * E - double(2 * n + 1) * e) * inv_r2;
+        g[n + 1] = -e;
     }
 }
 
-__device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
-    ewald_radial_e(r2, alpha, near, exp(-alpha * alpha * r2), g);
-}
-
-struct TableRec {
-    const double* t;
-    __device__ double operator[](int i) const { return load_uniform(t, i); }
+// The same constants computed in registers, for kernels without the table
+// (the training-data kernel).
+struct RadialConstsLocal {
+    double kk[6], g5, al2, ts;
+    __device__ explicit RadialConstsLocal(double al) {
+        const double SQRT_PI = 1.77245385090551602729;
+        al2 = al * al;
+        kk[0] = 1.0 / (al * SQRT_PI);
+        for (int m = 1; m < 6; ++m) kk[m] = kk[m - 1] * (-2.0 * al2);
+        g5 = 2.0 * al / SQRT_PI * (-32.0 * al2 * al2 * al2 * al2 * al2);
+        ts = (2.0 / al) * kErfcxScale;
+    }
+    __device__ double operator[](int i) const {
+        if (i < kEwInvNext) return c_ew.inv_odd[i - kEwInvOdd];
+        if (i < kEwInv2n1) return c_ew.inv_next[i - kEwInvNext];
+        if (i < kEwErfcx) return c_ew.inv_2n1[i - kEwInv2n1];
+        if (i < kEwK) return c_erfcx[i - kEwErfcx];
+        if (i < kEwG5) return kk[i - kEwK];
+        if (i == kEwG5) return g5;
+        if (i == kEwAl2) return al2;
+        return ts;
+    }
 };
 
-// Dynamic LDS of k_ewald: per thread, (hmax + 1) + 2 (2 hmax + 1) complex
-// phase factors.  Blocks of 128 threads up to hmax = 5 (57 KB), 64 above
-// (at most 44 KB at hmax = 8), so a block never needs more than 64 KB.
+__device__ void ewald_radial(double r2, double alpha, bool near, double g[6]) {
+    const RadialConstsLocal c(alpha);
+    if (near)
+        ewald_radial_near(c, r2, exp(-c[kEwAl2] * r2), g);
+    else
+        ewald_radial_far(c, r2, alpha, g);
+}
+
+// Dynamic LDS of k_ewald: per thread, 2 (hmax + 1) complex phase factors.
+// Blocks of 128 threads up to hmax = 5 (24 KB; 16 KB at hmax = 3), 64 above
+// (at most 18 KB at hmax = 8).
 constexpr int kEwaldThreads = 128;
 inline int ewald_threads(int hmax) { return hmax <= 5 ? kEwaldThreads : kEwaldThreads / 2; }
 inline size_t ewald_lds_bytes(int hmax) {
-    return sizeof(double2) * size_t(hmax + 1 + 2 * (2 * hmax + 1)) * size_t(ewald_threads(hmax));
+    return sizeof(double2) * size_t(2 * (hmax + 1)) * size_t(ewald_threads(hmax));
+}
+
+// One image's terms, order by order into the sums: phi += sum_n g_n P_n,
+// acc -= sum_n (g_{n+1} P_n R + g_n grad P_n), with the same grouping of
+// the moments as multipole_terms (each order's intermediates die before
+// the next order starts).
+__device__ __forceinline__ void ewald_real_terms(const TableRec& r, double x, double y, double z,
+                                                 const double (&g)[6], double& phi, double& ax,
+                                                 double& ay, double& az) {
+    double S = fma(g[2], r[1], g[1] * r[0]);
+    phi = fma(g[1], r[1], fma(g[0], r[0], phi));
+    const double xx = x * x, yy = y * y, zz = z * z;
+    {
+        const double h2x = r[2] * x + (r[3] * y + (r[4] * z + r[8]));
+        const double h2y = r[3] * x + (r[5] * y + (r[6] * z + r[9]));
+        const double h2z = r[4] * x + (r[6] * y + (r[7] * z + r[10]));
+        const double P2 = x * h2x + y * h2y + z * h2z + r[11];
+        phi = fma(g[2], P2, phi);
+        S = fma(g[3], P2, S);
+        ax -= g[2] * (2.0 * h2x - r[8]);
+        ay -= g[2] * (2.0 * h2y - r[9]);
+        az -= g[2] * (2.0 * h2z - r[10]);
+    }
+    {
+        const double qxy = 2.0 * x * y, qxz = 2.0 * x * z, qyz = 2.0 * y * z;
+        const double w4x = r[22] * x + r[23] * y + r[24] * z;
+        const double w4y = r[23] * x + r[25] * y + r[26] * z;
+        const double w4z = r[24] * x + r[26] * y + r[27] * z;
+        const double h3x = r[12] * xx + (r[15] * yy + (r[17] * zz + (r[13] * qxy + (r[14] * qxz +
+                           (r[16] * qyz + w4x)))));
+        const double h3y = r[13] * xx + (r[18] * yy + (r[20] * zz + (r[15] * qxy + (r[16] * qxz +
+                           (r[19] * qyz + w4y)))));
+        const double h3z = r[14] * xx + (r[19] * yy + (r[21] * zz + (r[16] * qxy + (r[17] * qxz +
+                           (r[20] * qyz + w4z)))));
+        const double P3 = x * h3x + y * h3y + z * h3z;
+        phi = fma(g[3], P3, phi);
+        S = fma(g[4], P3, S);
+        ax -= g[3] * (3.0 * h3x - w4x);
+        ay -= g[3] * (3.0 * h3y - w4y);
+        az -= g[3] * (3.0 * h3z - w4z);
+    }
+    {
+        const double x3 = 3.0 * x, y3 = 3.0 * y, z3 = 3.0 * z;
+        const double cxxx = xx * x, cxxy = xx * y3, cxxz = xx * z3, cxyy = yy * x3;
+        const double cxyz = 2.0 * x * y * z3;
+        const double cxzz = zz * x3, cyyy = yy * y, cyyz = yy * z3, cyzz = zz * y3, czzz = zz * z;
+        const double v4x = r[28] * cxxx + r[29] * cxxy + r[30] * cxxz + r[31] * cxyy +
+                           r[32] * cxyz + r[33] * cxzz + r[34] * cyyy + r[35] * cyyz +
+                           r[36] * cyzz + r[37] * czzz;
+        const double v4y = r[29] * cxxx + r[31] * cxxy + r[32] * cxxz + r[34] * cxyy +
+                           r[35] * cxyz + r[36] * cxzz + r[38] * cyyy + r[39] * cyyz +
+                           r[40] * cyzz + r[41] * czzz;
+        const double v4z = r[30] * cxxx + r[32] * cxxy + r[33] * cxxz + r[35] * cxyy +
+                           r[36] * cxyz + r[37] * cxzz + r[39] * cyyy + r[40] * cyyz +
+                           r[41] * cyzz + r[42] * czzz;
+        const double P4 = x * v4x + y * v4y + z * v4z;
+        phi = fma(g[4], P4, phi);
+        S = fma(g[5], P4, S);
+        const double g44 = 4.0 * g[4];
+        ax -= g44 * v4x;
+        ay -= g44 * v4y;
+        az -= g44 * v4z;
+    }
+    ax -= S * x;
+    ay -= S * y;
+    az -= S * z;
 }
 
 // The correction at particle i into acc and pot, or into the judge's
@@ -1524,6 +1661,7 @@ inline size_t ewald_lds_bytes(int hmax) {
 __device__ __forceinline__ void ewald_particle(const EwaldArgs& a, int64_t i, double* out,
                                                double2* ew_lds) {
     const TableRec rec{a.table};
+    const TableRec coef{a.table + kEwCoef};
     const double invL = 1.0 / a.L;
     double xi0, xi1, xi2;
     load_pos(a.pin, i, xi0, xi1, xi2);
@@ -1543,88 +1681,86 @@ __device__ __forceinline__ void ewald_particle(const EwaldArgs& a, int64_t i, do
         fya[k] = exp(-al2 * dy * dy);
         fza[k] = exp(-al2 * dz * dz);
     }
+    const int Rn = R < 1 ? R : 1;
+    for (int ix = -Rn; ix <= Rn; ++ix)
+        for (int iy = -Rn; iy <= Rn; ++iy)
+            for (int iz = -Rn; iz <= Rn; ++iz) {
+                // reload the table values per image (scalar loads, cheap)
+                // rather than keeping them live across the loop
+                asm volatile("" ::: "memory");
+                const double x = rx - ix, y = ry - iy, z = rz - iz;
+                const double r2 = x * x + y * y + z * z;
+                // wave-uniform selects, no indexed registers
+                const double fx = ix < 0 ? fxa[0] : (ix == 0 ? fxa[1] : fxa[2]);
+                const double fy = iy < 0 ? fya[0] : (iy == 0 ? fya[1] : fya[2]);
+                const double fz = iz < 0 ? fza[0] : (iz == 0 ? fza[1] : fza[2]);
+                double g[6];
+                ewald_radial_near(coef, r2, fx * fy * fz, g);
+                ewald_real_terms(rec, x, y, z, g, phi, ax, ay, az);
+            }
+    // outer shells (max |n_a| >= 2)
     for (int ix = -R; ix <= R; ++ix)
         for (int iy = -R; iy <= R; ++iy)
             for (int iz = -R; iz <= R; ++iz) {
-                // reload the 44 table values per image (scalar loads, cheap)
-                // rather than keeping them live across the loop
+                if (ix >= -1 && ix <= 1 && iy >= -1 && iy <= 1 && iz >= -1 && iz <= 1) continue;
                 asm volatile("" ::: "memory");
-                const bool near = ix >= -1 && ix <= 1 && iy >= -1 && iy <= 1 && iz >= -1 && iz <= 1;
                 const double x = rx - ix, y = ry - iy, z = rz - iz;
                 const double r2 = x * x + y * y + z * z;
-                double E;
-                if (near) {  // wave-uniform selects, no indexed registers
-                    const double fx = ix < 0 ? fxa[0] : (ix == 0 ? fxa[1] : fxa[2]);
-                    const double fy = iy < 0 ? fya[0] : (iy == 0 ? fya[1] : fya[2]);
-                    const double fz = iz < 0 ? fza[0] : (iz == 0 ? fza[1] : fza[2]);
-                    E = fx * fy * fz;
-                } else {
-                    E = exp(-al2 * r2);
-                }
                 double g[6];
-                ewald_radial_e(r2, a.alpha, near, E, g);
-                double P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z, v4x, v4y, v4z;
-                multipole_terms<double>(rec, x, y, z, P2, P3, P4, g2x, g2y, g2z, g3x, g3y, g3z,
-                                        v4x, v4y, v4z);
-                // psi enters with a + sign: phi += sum_n g_n P_n, acc = -grad
-                phi += g[0] * rec[0] + g[1] * rec[1] + g[2] * P2 + g[3] * P3 + g[4] * P4;
-                const double S = g[1] * rec[0] + g[2] * rec[1] + g[3] * P2 + g[4] * P3 + g[5] * P4;
-                const double g44 = 4.0 * g[4];
-                ax -= S * x + g[2] * g2x + g[3] * g3x + g44 * v4x;
-                ay -= S * y + g[2] * g2y + g[3] * g3y + g44 * v4y;
-                az -= S * z + g[2] * g2z + g[3] * g3z + g44 * v4z;
+                ewald_radial_far(coef, r2, a.alpha, g);
+                ewald_real_terms(rec, x, y, z, g, phi, ax, ay, az);
             }
-    // k space over the table rows.  Each thread keeps e^{i 2 pi k r_a} for
-    // k = 0..hmax (x) and k = -hmax..hmax (y, z) in LDS (its own column,
-    // built by repeated rotation); a row multiplies one entry per axis.
+    // k space over the table rows, which come in order of hx (then hy, hz).
+    // The factor e^{i 2 pi hx x} advances in registers as hx grows; each
+    // thread keeps e^{i 2 pi k r_a} for k = 0..hmax (y, z) in LDS (its own
+    // column, built by repeated rotation), negative k by conjugation.
     const int hm = a.hmax, T = blockDim.x, tid = threadIdx.x;
-    double2* ex = ew_lds;               // [hm + 1][T]
-    double2* ey = ex + (hm + 1) * T;    // [2 hm + 1][T], index hy + hm
-    double2* ez = ey + (2 * hm + 1) * T;
+    double2* ey = ew_lds;             // [hm + 1][T]
+    double2* ez = ey + (hm + 1) * T;  // [hm + 1][T]
+    double s1x, c1x;
+    sincospi(2.0 * rx, &s1x, &c1x);
     {
         double s1, c1;
-        sincospi(2.0 * rx, &s1, &c1);
-        double c = 1.0, s = 0.0;
-        ex[tid] = make_double2(1.0, 0.0);
-        for (int k = 1; k <= hm; ++k) {
-            const double t = c * c1 - s * s1;
-            s = s * c1 + c * s1;
-            c = t;
-            ex[k * T + tid] = make_double2(c, s);
-        }
         sincospi(2.0 * ry, &s1, &c1);
-        c = 1.0;
-        s = 0.0;
-        ey[hm * T + tid] = make_double2(1.0, 0.0);
+        double c = 1.0, s = 0.0;
+        ey[tid] = make_double2(1.0, 0.0);
         for (int k = 1; k <= hm; ++k) {
             const double t = c * c1 - s * s1;
             s = s * c1 + c * s1;
             c = t;
-            ey[(hm + k) * T + tid] = make_double2(c, s);
-            ey[(hm - k) * T + tid] = make_double2(c, -s);
+            ey[k * T + tid] = make_double2(c, s);
         }
         sincospi(2.0 * rz, &s1, &c1);
         c = 1.0;
         s = 0.0;
-        ez[hm * T + tid] = make_double2(1.0, 0.0);
+        ez[tid] = make_double2(1.0, 0.0);
         for (int k = 1; k <= hm; ++k) {
             const double t = c * c1 - s * s1;
             s = s * c1 + c * s1;
             c = t;
-            ez[(hm + k) * T + tid] = make_double2(c, s);
-            ez[(hm - k) * T + tid] = make_double2(c, -s);
+            ez[k * T + tid] = make_double2(c, s);
         }
     }
     const double* tab = a.table + 64;
     const int64_t* key = reinterpret_cast<const int64_t*>(tab);
     const int nk = int(load_uniform(a.table, 44));
+    double cx = 1.0, sx = 0.0;
+    int hx_at = 0;
     for (int q = 0; q < nk; ++q) {
         const int row = 8 * q;
         const int64_t kk = load_uniform(key, row + 7);  // hx | (hy + hm) << 8 | (hz + hm) << 16
-        const double2 px = ex[int(kk & 0xff) * T + tid];
-        const double2 py = ey[int((kk >> 8) & 0xff) * T + tid];
-        const double2 pz = ez[int((kk >> 16) & 0xff) * T + tid];
-        const double cxy = px.x * py.x - px.y * py.y, sxy = px.y * py.x + px.x * py.y;
+        const int hx = int(kk & 0xff);
+        for (; hx_at < hx; ++hx_at) {  // wave-uniform
+            const double t = cx * c1x - sx * s1x;
+            sx = sx * c1x + cx * s1x;
+            cx = t;
+        }
+        const int jy = int((kk >> 8) & 0xff) - hm, jz = int((kk >> 16) & 0xff) - hm;
+        double2 py = ey[(jy < 0 ? -jy : jy) * T + tid];
+        double2 pz = ez[(jz < 0 ? -jz : jz) * T + tid];
+        if (jy < 0) py.y = -py.y;
+        if (jz < 0) pz.y = -pz.y;
+        const double cxy = cx * py.x - sx * py.y, sxy = sx * py.x + cx * py.y;
         const double c = cxy * pz.x - sxy * pz.y, s = sxy * pz.x + cxy * pz.y;
         phi += load_uniform(tab, row + 3) * c + load_uniform(tab, row + 4) * s;
         const double f = load_uniform(tab, row + 5) * s + load_uniform(tab, row + 6) * c;
@@ -1694,21 +1830,25 @@ constexpr int kEwaldBesideBlocksPerCU = 2;  // 2 waves each: one per SIMD
 __global__ void __launch_bounds__(kEwaldThreads) k_ewald_beside(EwaldArgs a) {
     extern __shared__ double2 ew_lds[];
     for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < a.n;
-         j += int64_t(gridDim.x) * blockDim.x)
+         j += int64_t(gridDim.x) * blockDim.x) {
+        asm volatile("" ::: "memory");  // table reads stay inside the loop
         ewald_particle(a, j, nullptr, ew_lds);
+    }
 }
 
 // The listed active particles (a mask is in use), over a bounded grid: a
 // grid covering every particle would spend most of its time starting
 // blocks that exit, each holding its LDS tables while it does.
-__global__ void __launch_bounds__(kEwaldThreads) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kEwaldThreads) __attribute__((amdgpu_waves_per_eu(3)))
 k_ewald_list(EwaldArgs a) {
     extern __shared__ double2 ew_lds[];
     if (a.gate && a.gate->ew_fallback == 0) return;
     const int64_t count = int64_t(a.ctl->n_list);
     for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < count;
-         j += int64_t(gridDim.x) * blockDim.x)
+         j += int64_t(gridDim.x) * blockDim.x) {
+        asm volatile("" ::: "memory");  // table reads stay inside the loop
         ewald_particle(a, a.list[j], nullptr, ew_lds);
+    }
 }
 
 // The buffered correction added to the PP + PC sums, in double and rounded
@@ -2309,9 +2449,11 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
             // PP + PC variant the branch starts with the compute (the
             // correction reads only the caller's positions and root moments)
             // and takes one wave per SIMD before the PP + PC kernel fills the
-            // GPU; next to a 3-wave variant (no room for that wave) or with a
-            // mask (the list of active particles comes from phase 0) it starts
-            // after phase 0 and fills the PP + PC kernel's tail.
+            // GPU.  Next to a 3-wave variant, or with a mask (the list of
+            // active particles comes from phase 0), it starts after phase 0
+            // and fills the PP + PC kernel's tail: a correction wave beside
+            // two waves of a 3-wave variant (room enough for its registers)
+            // made the 512^3 clustered step 24 % slower than the tail.
             L->overlap = 1;
             L->early = (!e.list && kVariantWaves[L->variant] == 2) ? 1 : 0;
             e.ewbuf = reinterpret_cast<double*>(w + c->lay.ewbuf);
