@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--ewald-study", action="store_true",
                     help="instead of the throughput line: exact vs learned Ewald correction, "
                          "time against force error, on the chosen config (default 4)")
+    ap.add_argument("--fmm-only", action="store_true",
+                    help="instead of the throughput line: only the fast-multipole leg "
+                         "(128^3 clustered set, against the bucket walk), as one JSON line")
     ap.add_argument("--train-samples", type=int, default=2_000_000)
     ap.add_argument("--train-epochs", type=int, default=30)
     ap.add_argument("--substep-ewald", choices=("fallback", "exact"), default="fallback",
@@ -91,6 +94,11 @@ def main():
 
     if args.ewald_study:
         ewald_study(args)
+        return
+    if args.fmm_only:
+        ctx = mg.Context(0)
+        print(json.dumps({"fmm": fmm_leg(ctx, args)}), flush=True)
+        ctx.close()
         return
     if args.config == 5:
         substeps(args)
