@@ -405,49 +405,72 @@ __global__ void __launch_bounds__(256) k_need_clear(StageArgs a) {
         w[i] = 0u;
 }
 
-__global__ void __launch_bounds__(256) k_need_mark(StageArgs a) {
-    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStageLanes;
-    const int sl = int(threadIdx.x % kStageLanes);
-    if (b >= a.n_bucket) return;  // whole groups
-    const int64_t s = a.bucket_cell[b];
-    if (s < 0 || s >= a.n_cell) return;
-    const CellInfo ci = cell_info(a, s);
-    const bool act = group_or(sl < ci.count && a.active[ci.first + sl] ? 1 : 0) != 0;
-    if (!act) return;
-    if (sl == 0) a.need_src[s] = 1;
-    const int64_t e0 = a.pp_off[b], e1 = a.pp_off[b + 1];
-    if (e0 >= 0 && e0 <= e1 && e1 <= a.n_pp)
-        for (int64_t e = e0 + sl; e < e1; e += kStageLanes) {
-            const int32_t src = a.pp_src[e];
-            if (src >= 0 && src < a.n_cell) a.need_src[src] = 1;
+// One lane per bucket finds whether any of its particles is active (a
+// masked compute touches a few per cent of the buckets: for most of them
+// the test is all the work); then the active buckets of the wave's 64 have
+// their lists marked by groups of 16 lanes, four buckets at a time, each
+// lane with kStageRound entries in flight.
+template <typename Mark>
+__device__ __forceinline__ void mark_range(const int32_t* src, int64_t e0, int64_t e1,
+                                           int64_t n_cell, int sl, Mark&& mark) {
+    for (int64_t eb = e0 + sl; eb < e1; eb += kStageRound * kStageLanes) {
+        int32_t v[kStageRound];
+#pragma unroll
+        for (int u = 0; u < kStageRound; ++u) {
+            const int64_t e = eb + u * kStageLanes;
+            v[u] = e < e1 ? src[e] : -1;
         }
-    const int64_t g0 = a.pc_off[b], g1 = a.pc_off[b + 1];
-    if (g0 >= 0 && g0 <= g1 && g1 <= a.n_pc)
-        for (int64_t e = g0 + sl; e < g1; e += kStageLanes) {
-            const int32_t src = a.pc_src[e];
-            if (src >= 0 && src < a.n_cell) a.need_rec[src] = 1;
-        }
+#pragma unroll
+        for (int u = 0; u < kStageRound; ++u)
+            if (v[u] >= 0 && v[u] < n_cell) mark(v[u]);
+    }
 }
 
-__global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
-    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStageLanes;
-    const int sl = int(threadIdx.x % kStageLanes);
-    if (b >= a.n_bucket) return;  // whole groups: the first n_bucket groups are in range
-    const int64_t s = a.bucket_cell[b];
-    const bool sink_ok = s >= 0 && s < a.n_cell;
-    // (for a masked compute the CellInfo of inactive sinks is not staged)
-    const CellInfo ci = !sink_ok ? CellInfo{0.0, 0.0, 0.0, 0, 0}
-                                 : (a.active ? cell_info(a, s) : a.cinfo[s]);
-    // with a mask: whether any sink is active (only then are the bucket's
-    // lists staged), and whether its particles are read at all
-    bool act = true, stage_sinks = true;
-    if (a.active) {
-        act = group_or(sl < ci.count && a.active[ci.first + sl] ? 1 : 0) != 0;
-        stage_sinks = sink_ok && a.need_src[s];
+__global__ void __launch_bounds__(256) k_need_mark(StageArgs a) {
+    const int lane = int(threadIdx.x & (kWave - 1));
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int s = -1;
+    bool act = false;
+    if (b < a.n_bucket) {
+        const int64_t c = a.bucket_cell[b];
+        if (c >= 0 && c < a.n_cell) {
+            s = int(c);
+            const CellInfo ci = cell_info(a, c);
+            for (int k = 0; k < ci.count; ++k) act |= a.active[ci.first + k] != 0;
+        }
     }
+    const int64_t b0 = b - lane;
+    const int g = lane / kStageLanes, sl = lane % kStageLanes;
+    for (uint64_t todo = __ballot(act); todo;) {
+        uint64_t m = todo;  // this group's bucket: the g-th remaining one
+        for (int t = 0; t < kWave / kStageLanes - 1; ++t)
+            if (t < g) m &= m - 1;
+        for (int t = 0; t < kWave / kStageLanes; ++t) todo &= todo - 1;  // (wave-uniform)
+        const int l = m ? __builtin_ctzll(m) : 0;
+        const int sc = __shfl(s, l);
+        if (!m) continue;
+        const int64_t bb = b0 + l;
+        if (sl == 0) a.need_src[sc] = 1;
+        const int64_t e0 = a.pp_off[bb], e1 = a.pp_off[bb + 1];
+        if (e0 >= 0 && e0 <= e1 && e1 <= a.n_pp)
+            mark_range(a.pp_src, e0, e1, a.n_cell, sl, [&](int32_t c) { a.need_src[c] = 1; });
+        const int64_t g0 = a.pc_off[bb], g1 = a.pc_off[bb + 1];
+        if (g0 >= 0 && g0 <= g1 && g1 <= a.n_pc)
+            mark_range(a.pc_src, g0, g1, a.n_cell, sl, [&](int32_t c) { a.need_rec[c] = 1; });
+    }
+}
+
+// The staging of bucket b by a group of 16 lanes (lane sl of the group):
+// its sink particles when stage_sinks, its PP entries and the check of its
+// PC range when act, and, when write_work, its work descriptor and error
+// bits.  A group with nothing to do passes act, stage_sinks and write_work
+// false and only takes part in the group reductions.
+__device__ __forceinline__ void stage_bucket_group(const StageArgs& a, int64_t b, int sl,
+                                                   int64_t s, bool sink_ok, const CellInfo& ci,
+                                                   bool act, bool stage_sinks, bool write_work) {
     // the sink particles
     if (ci.count == 0) {
-        if (sl == 0) atomicOr(&a.ctl->err, kErrTree);
+        if (sl == 0 && write_work) atomicOr(&a.ctl->err, kErrTree);
     } else if (sl < ci.count && stage_sinks) {
         const int64_t p = ci.first + sl;
         double x, y, z;
@@ -506,7 +529,7 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
     bad = group_or(bad);
     self = group_or(self);
     nsrc = group_sum(nsrc);
-    if (sl == 0) {
+    if (sl == 0 && write_work) {
         if (bad) atomicOr(&a.ctl->err, kErrList);
         BucketWork w;
         w.first = ci.count ? ci.first : 0;
@@ -518,6 +541,71 @@ __global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
         w.pc0 = pc_ok && sink_ok ? g0 : 0;
         w.pc1 = pc_ok && sink_ok ? g1 : 0;
         a.work[b] = w;
+    }
+}
+
+// Without a mask: every bucket, 16 lanes each.
+__global__ void __launch_bounds__(256) k_stage_bucket(StageArgs a) {
+    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / kStageLanes;
+    const int sl = int(threadIdx.x % kStageLanes);
+    if (b >= a.n_bucket) return;  // whole groups: the first n_bucket groups are in range
+    const int64_t s = a.bucket_cell[b];
+    const bool sink_ok = s >= 0 && s < a.n_cell;
+    const CellInfo ci = sink_ok ? a.cinfo[s] : CellInfo{0.0, 0.0, 0.0, 0, 0};
+    stage_bucket_group(a, b, sl, s, sink_ok, ci, true, true, true);
+}
+
+// With a mask: one lane per bucket finds whether it is active and whether
+// its particles are read (as PP sources of active buckets), and writes
+// the descriptor of an inactive bucket (no lists); the buckets with
+// anything to stage then go through the 16-lane staging, four at a time.
+__global__ void __launch_bounds__(256) k_stage_bucket_masked(StageArgs a) {
+    const int lane = int(threadIdx.x & (kWave - 1));
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t b0 = b - lane;
+    int s = -1;
+    CellInfo ci{0.0, 0.0, 0.0, 0, 0};
+    bool act = false, stage = false;
+    if (b < a.n_bucket) {
+        const int64_t c = a.bucket_cell[b];
+        const bool sink_ok = c >= 0 && c < a.n_cell;
+        if (sink_ok) {
+            s = int(c);
+            ci = cell_info(a, c);
+            for (int k = 0; k < ci.count; ++k) act |= a.active[ci.first + k] != 0;
+            stage = a.need_src[c] != 0;
+        }
+        if (!act) {
+            if (ci.count == 0) atomicOr(&a.ctl->err, kErrTree);
+            if (!sink_ok) atomicOr(&a.ctl->err, kErrList);
+            BucketWork w;
+            w.first = ci.count ? ci.first : 0;
+            w.nsink = ci.count;
+            w.self = 0;
+            w.nsrc = 0;
+            w.pp0 = w.pp1 = w.pc0 = w.pc1 = 0;
+            a.work[b] = w;
+        }
+    }
+    const int g = lane / kStageLanes, sl = lane % kStageLanes;
+    for (uint64_t todo = __ballot(act || stage); todo;) {
+        uint64_t m = todo;  // this group's bucket: the g-th remaining one
+        for (int t = 0; t < kWave / kStageLanes - 1; ++t)
+            if (t < g) m &= m - 1;
+        for (int t = 0; t < kWave / kStageLanes; ++t) todo &= todo - 1;  // (wave-uniform)
+        const bool valid = m != 0;
+        const int l = valid ? __builtin_ctzll(m) : 0;
+        CellInfo cb;
+        cb.cx = __shfl(ci.cx, l);
+        cb.cy = __shfl(ci.cy, l);
+        cb.cz = __shfl(ci.cz, l);
+        cb.first = __shfl(ci.first, l);
+        cb.count = __shfl(ci.count, l);
+        const int sb = __shfl(s, l);
+        const bool ab = __shfl(act ? 1 : 0, l) != 0 && valid;
+        const bool stb = __shfl(stage ? 1 : 0, l) != 0 && valid;
+        stage_bucket_group(a, b0 + l, sl, sb, true, valid ? cb : CellInfo{0.0, 0.0, 0.0, 0, 0},
+                           ab, stb, ab);
     }
 }
 
@@ -2483,17 +2571,22 @@ static void make_launch(mgrav_ctx* c, int parts, float* acc, float* pot, LaunchS
 
 // The staging kernels of mgrav_bind (positions, cells, PP and PC entries).
 static void enqueue_stage(hipStream_t st, const StageArgs& a) {
-    const int64_t nb = a.n_bucket * kStageLanes;
+    const unsigned per_bucket = unsigned((a.n_bucket + 255) / 256);  // one thread per bucket
     if (a.active) {
         const int64_t words = (2 * a.n_cell + 3) / 4;
         const int64_t gb = (words + 255) / 256;
         hipLaunchKernelGGL(k_need_clear, dim3(unsigned(gb < 1024 ? gb : 1024)), dim3(256), 0, st,
                            a);
-        hipLaunchKernelGGL(k_need_mark, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_need_mark, dim3(per_bucket), dim3(256), 0, st, a);
     }
     hipLaunchKernelGGL(k_stage_cells, dim3(unsigned((a.n_cell + 255) / 256)), dim3(256), 0, st,
                        a);
-    hipLaunchKernelGGL(k_stage_bucket, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, a);
+    if (a.active) {
+        hipLaunchKernelGGL(k_stage_bucket_masked, dim3(per_bucket), dim3(256), 0, st, a);
+    } else {
+        const int64_t nb = a.n_bucket * kStageLanes;
+        hipLaunchKernelGGL(k_stage_bucket, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, a);
+    }
 }
 
 // Exact correction of every active particle: one thread per particle, or,
