@@ -906,12 +906,49 @@ def kdk_leg(ctx, store, m_uniform, eps, cfg, amag, rung_max):
     log(f"kdk: base step {dt_base:.3e} of 2^{rung_max} substeps in {t_step:.2f}s "
         f"({updates} particle updates), rungs {rungs.tolist()}, substeps "
         f"{[(s['active'], s['dual_tree'], round(s['seconds'], 3)) for s in subs]}")
+    # the fixed tree kept (Sec. 3.2): the deepest rung's particles as the
+    # very active group; the forest of one call against the fixed tree
+    # built once and the very active tree rebuilt alone behind it (the
+    # integrator above rebuilds both)
+    kept = None
+    g = (it.store.rung >= rung_max).to(torch.uint8)
+    n_va = int(g.sum().item())
+    if 0 < n_va < it.n:
+        pos = ctx.store_decode(it.store)
+        mass = torch.full((it.n,), m_uniform, dtype=torch.float64, device=pos.device)
+        t_forest, t_rebuild = [], []
+        for rep in range(2):  # the second build is kept for the comparison
+            if rep:
+                del tf
+            t0 = time.perf_counter()
+            tf = ctx.tree_build(pos, mass, 1.0, cfg.bucket, group_dev=g)
+            torch.cuda.synchronize()
+            t_forest.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        kf = ctx.forest_keep(pos, mass, 1.0, g, cfg.bucket)
+        torch.cuda.synchronize()
+        t_keep = time.perf_counter() - t0
+        for rep in range(2):
+            t0 = time.perf_counter()
+            tk = ctx.forest_rebuild(kf, pos, mass)
+            torch.cuda.synchronize()
+            t_rebuild.append(time.perf_counter() - t0)
+        same = all(torch.equal(getattr(tk, f), getattr(tf, f))
+                   for f in ("perm", "cell_first", "child", "bucket_cell", "mom"))
+        kept = {"very_active": n_va, "seconds_forest_one_call": min(t_forest),
+                "seconds_fixed_tree_kept": t_keep,
+                "seconds_very_active_tree_rebuilt": min(t_rebuild),
+                "equal_to_one_call_forest": same}
+        log(f"kdk: fixed tree kept: forest in one call {min(t_forest):.3f}s, fixed tree "
+            f"{t_keep:.3f}s once, very active tree ({n_va} particles) rebuilt "
+            f"{min(t_rebuild):.4f}s; equal arrays {same}")
+        del tf, tk, kf, pos, mass
     del it
     torch.cuda.empty_cache()
     return {"workload": f"{cfg.name} from rest, rungs 0..{rung_max}, dt_base {dt_base:.4e}",
             "seconds_first_force": t_start, "seconds_base_step": t_step,
             "particle_updates_per_s": updates / t_step, "rungs_after": rungs.tolist(),
-            "substeps": subs,
+            "substeps": subs, "fixed_tree_kept": kept,
             "note": "a substep = drift, device tree (both trees below 5 % active), lists, "
                     "bind, PP + PC + Ewald for the active particles, kick and new rungs"}
 

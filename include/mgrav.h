@@ -202,6 +202,25 @@ mgrav_status mgrav_tree_build(mgrav_ctx *ctx, int64_t n, const double *pos, cons
                               size_t bytes, int64_t cap, const mgrav_tree_dev *out,
                               int64_t *n_cell, int64_t *n_bucket, int64_t *n_cell_first);
 
+/* Sec. 3.2 keeps the fixed tree and rebuilds only the very active one.
+ * mgrav_tree_offset turns a tree that mgrav_tree_build built alone, from
+ * the particles ids[0 .. n_particles-1] of a forest's input (device int64,
+ * in input order), into one tree of that forest, in place: cell_first +=
+ * particle_offset, child (where >= 0) and bucket_cell += cell_offset,
+ * perm[i] = ids[perm[i]].  The arrays of `t` are device memory, sized
+ * n_cell (cell_first, child), n_bucket (bucket_cell) and n_particles
+ * (perm).  Built this way into consecutive ranges of one set of arrays
+ * (the group-0 particles with offsets 0, then the others with offsets
+ * the first tree's cell and particle counts), two trees equal, array for
+ * array, the forest one mgrav_tree_build call with the group array
+ * writes, when the box is periodic (an open forest takes the root box of
+ * all particles, a tree built alone that of its own).  Blocking.
+ * INVALID_ARG for null pointers, sizes out of range, fewer ids than
+ * particles or a perm entry outside [0, n_ids). */
+mgrav_status mgrav_tree_offset(mgrav_ctx *ctx, const mgrav_tree_dev *t, int64_t n_cell,
+                               int64_t n_bucket, int64_t n_particles, int64_t cell_offset,
+                               int64_t particle_offset, const int64_t *ids, int64_t n_ids);
+
 /* The checklist walk of mgrav_lists_count_host / _fill_host on the
  * device, for the sink buckets sink_cell[n_sink] (cells, device memory;
  * for one tree its bucket_cell, for a forest the second tree's buckets),

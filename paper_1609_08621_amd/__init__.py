@@ -184,6 +184,9 @@ def _declare():
                                    ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     L.mgrav_lists_workspace_size.restype = _I
     L.mgrav_lists_workspace_size.argtypes = [_I64, _I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mgrav_tree_offset.restype = _I
+    L.mgrav_tree_offset.argtypes = [_P, ctypes.POINTER(TreeDev), _I64, _I64, _I64, _I64, _I64,
+                                    _P, _I64]
     L.mgrav_lists_count.restype = _I
     L.mgrav_lists_count.argtypes = [_P, ctypes.POINTER(Walk), _P, ctypes.c_size_t, _P, _P,
                                     ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
@@ -231,7 +234,8 @@ EXPORTS = (
     "mgrav_mlp_get_weights", "mgrav_mlp_forward", "mgrav_mlp_backward", "mgrav_mlp_train",
     "mgrav_interact_variants", "mgrav_interact_variant_info", "mgrav_set_interact_variant",
     "mgrav_autotune", "mgrav_set_launch_mode", "mgrav_set_queue_order", "mgrav_watchdog_poll",
-    "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_lists_workspace_size",
+    "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_tree_offset",
+    "mgrav_lists_workspace_size",
     "mgrav_lists_count", "mgrav_lists_fill", "mgrav_store_encode", "mgrav_store_decode",
     "mgrav_store_permute", "mgrav_store_drift", "mgrav_store_kick", "mgrav_store_rungs",
     "mgrav_store_active", "mgrav_fmm_lists_count_host", "mgrav_fmm_lists_fill_host",
@@ -333,6 +337,22 @@ class ParticleStore:
     @property
     def rung(self):
         return self.aux & 0xff
+
+
+@dataclasses.dataclass
+class KeptForest:
+    """A fixed tree kept for a forest (Sec. 3.2): the forest's arrays with
+    the first tree in place and room for the second (``Context.forest_keep``,
+    ``Context.forest_rebuild``)."""
+
+    arrays: dict
+    n_cell_first: int
+    n_bucket_first: int
+    n_first: int
+    ids_second: object
+    cap_second: int
+    box_L: float
+    bucket: int
 
 
 @dataclasses.dataclass
@@ -579,6 +599,45 @@ class Context:
         torch.cuda.synchronize(dev)
         return keep, p
 
+    def _tree_build_into(self, pos_dev, mass_dev, box_L: float, bucket: int, group_dev,
+                         cap: int, out: dict):
+        """One mgrav_tree_build call writing into the tensors of ``out`` (room
+        for ``cap`` cells).  Returns (cells, buckets, first tree's cells), or
+        None when the tree needs more than ``cap`` cells."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        n = int(pos_dev.shape[0])
+        sz = ctypes.c_size_t(0)
+        _check(_lib.mgrav_tree_workspace_size(n, int(bucket), int(cap), ctypes.byref(sz)))
+        ws = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
+        td = TreeDev(*[out[f].data_ptr() for f, _ in TreeDev._fields_])
+        nc, nb, nf = _I64(0), _I64(0), _I64(0)
+        st = _lib.mgrav_tree_build(self._h, n, _P(pos_dev.data_ptr()), _P(mass_dev.data_ptr()),
+                                   _P(group_dev.data_ptr()) if group_dev is not None else None,
+                                   float(box_L), int(bucket), _P(ws.data_ptr()),
+                                   ctypes.c_size_t(ws.numel()), int(cap), ctypes.byref(td),
+                                   ctypes.byref(nc), ctypes.byref(nb), ctypes.byref(nf))
+        del ws
+        if st == OK:
+            return int(nc.value), int(nb.value), int(nf.value)
+        msg = _lib.mgrav_last_error(self._h) or b""
+        if st == ERR_INVALID_ARG and b"capacity" in msg:
+            return None
+        _check(st, self._h)
+
+    def _tree_out(self, n: int, cap: int) -> dict:
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        return dict(perm=torch.empty(n, dtype=torch.int64, device=dev),
+                    pos=torch.empty((n, 3), **f64), mass=torch.empty(n, **f64),
+                    cell_first=torch.empty(cap, dtype=torch.int64, device=dev),
+                    cell_count=torch.empty(cap, dtype=torch.int32, device=dev),
+                    child=torch.empty((cap, 2), dtype=torch.int32, device=dev),
+                    com=torch.empty((cap, 3), **f64), bmax=torch.empty(cap, **f64),
+                    bbox=torch.empty((cap, 6), **f64), mom=torch.empty((cap, 32), **f64),
+                    bucket_cell=torch.empty(cap, dtype=torch.int32, device=dev))
+
     def tree_build(self, pos_dev, mass_dev, box_L: float, bucket: int = 16, group_dev=None,
                    cap: Optional[int] = None):
         """The tree (or, with ``group_dev``, the two-tree forest of Sec. 3.2)
@@ -594,37 +653,77 @@ class Context:
                                                                      2 * n + 2)})
         self.stream.wait_stream(torch.cuda.current_stream(dev))
         for k, cp in enumerate(caps):
-            sz = ctypes.c_size_t(0)
-            _check(_lib.mgrav_tree_workspace_size(n, int(bucket), int(cp), ctypes.byref(sz)))
-            ws = torch.empty(int(sz.value), dtype=torch.uint8, device=dev)
-            f64 = dict(dtype=torch.float64, device=dev)
-            out = dict(perm=torch.empty(n, dtype=torch.int64, device=dev),
-                       pos=torch.empty((n, 3), **f64), mass=torch.empty(n, **f64),
-                       cell_first=torch.empty(cp, dtype=torch.int64, device=dev),
-                       cell_count=torch.empty(cp, dtype=torch.int32, device=dev),
-                       child=torch.empty((cp, 2), dtype=torch.int32, device=dev),
-                       com=torch.empty((cp, 3), **f64), bmax=torch.empty(cp, **f64),
-                       bbox=torch.empty((cp, 6), **f64), mom=torch.empty((cp, 32), **f64),
-                       bucket_cell=torch.empty(cp, dtype=torch.int32, device=dev))
-            td = TreeDev(*[out[f].data_ptr() for f, _ in TreeDev._fields_])
-            nc, nb, nf = _I64(0), _I64(0), _I64(0)
-            st = _lib.mgrav_tree_build(self._h, n, _P(pos_dev.data_ptr()),
-                                       _P(mass_dev.data_ptr()),
-                                       _P(group_dev.data_ptr()) if group_dev is not None else None,
-                                       float(box_L), int(bucket), _P(ws.data_ptr()),
-                                       ctypes.c_size_t(ws.numel()), int(cp), ctypes.byref(td),
-                                       ctypes.byref(nc), ctypes.byref(nb), ctypes.byref(nf))
-            del ws
-            if st == OK:
+            out = self._tree_out(n, cp)
+            got = self._tree_build_into(pos_dev, mass_dev, box_L, bucket, group_dev, cp, out)
+            if got is not None:
                 break
-            msg = _lib.mgrav_last_error(self._h) or b""
-            if st != ERR_INVALID_ARG or b"capacity" not in msg or k == len(caps) - 1:
-                _check(st, self._h)
-        c, b = int(nc.value), int(nb.value)
+            if k == len(caps) - 1:
+                raise MgravError(ERR_INVALID_ARG, "tree: capacity")
+        c, b, nf = got
         trim = {f: (v if f in ("perm", "pos", "mass") else v[:(b if f == "bucket_cell" else c)])
                 for f, v in out.items()}
-        return DeviceTree(**trim, box_L=float(box_L), n_cell_first=int(nf.value),
+        return DeviceTree(**trim, box_L=float(box_L), n_cell_first=nf,
                           grouped=group_dev is not None)
+
+    def _tree_offset(self, views: dict, n_cell: int, n_bucket: int, n_part: int,
+                     cell_offset: int, particle_offset: int, ids):
+        td = TreeDev(*[views[f].data_ptr() for f, _ in TreeDev._fields_])
+        _check(_lib.mgrav_tree_offset(self._h, ctypes.byref(td), int(n_cell), int(n_bucket),
+                                      int(n_part), int(cell_offset), int(particle_offset),
+                                      _P(ids.data_ptr()), int(ids.numel())), self._h)
+
+    def forest_keep(self, pos_dev, mass_dev, box_L: float, group_dev, bucket: int = 16):
+        """The fixed tree of Sec. 3.2 built once: the tree of the group-0
+        particles alone (periodic box), renumbered as the first tree of the
+        forest over all particles and stored with room for a second tree of
+        the other particles (``forest_rebuild`` adds it)."""
+        torch = self._torch
+        if not box_L > 0:
+            raise ValueError("forest_keep: a periodic box is needed (an open forest takes the "
+                             "root box of all particles)")
+        n = int(pos_dev.shape[0])
+        g = group_dev.to(torch.bool)
+        ids0 = torch.nonzero(~g).flatten()
+        ids1 = torch.nonzero(g).flatten()
+        n0, n1 = int(ids0.numel()), int(ids1.numel())
+        if n0 == 0 or n1 == 0:
+            raise ValueError("forest_keep: both groups must be non-empty")
+        t0 = self.tree_build(pos_dev.index_select(0, ids0), mass_dev.index_select(0, ids0),
+                             box_L, bucket)
+        nc0, nb0 = int(t0.cell_first.shape[0]), int(t0.bucket_cell.shape[0])
+        fields0 = {f.name: getattr(t0, f.name) for f in dataclasses.fields(t0)}
+        self._tree_offset(fields0, nc0, nb0, n0, 0, 0, ids0)
+        cap1 = 2 * n1 + 2
+        arrays = self._tree_out(n, nc0 + cap1)
+        for f, v in arrays.items():
+            src = getattr(t0, f)
+            v[:src.shape[0]].copy_(src)
+        return KeptForest(arrays=arrays, n_cell_first=nc0, n_bucket_first=nb0, n_first=n0,
+                          ids_second=ids1, cap_second=cap1, box_L=float(box_L), bucket=bucket)
+
+    def forest_rebuild(self, kf, pos_dev, mass_dev):
+        """The very active tree of Sec. 3.2 rebuilt alone from the group != 0
+        particles of pos_dev / mass_dev (input order, current positions) and
+        put behind the kept fixed tree.  Returns the forest as a DeviceTree
+        (views of the kept arrays, valid until the next rebuild)."""
+        torch = self._torch
+        dev = torch.device("cuda", self.device)
+        ids = kf.ids_second
+        p1 = pos_dev.index_select(0, ids).contiguous()
+        m1 = mass_dev.index_select(0, ids).contiguous()
+        nc0, nb0, n0 = kf.n_cell_first, kf.n_bucket_first, kf.n_first
+        A = kf.arrays
+        views = {f: (v[n0:] if f in ("perm", "pos", "mass") else
+                     v[(nb0 if f == "bucket_cell" else nc0):]) for f, v in A.items()}
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        got = self._tree_build_into(p1, m1, kf.box_L, kf.bucket, None, kf.cap_second, views)
+        if got is None:  # cannot happen with room for 2 n + 2 cells
+            raise MgravError(ERR_INVALID_ARG, "forest_rebuild: capacity")
+        nc1, nb1, _ = got
+        self._tree_offset(views, nc1, nb1, int(ids.numel()), nc0, n0, ids)
+        trim = {f: (v if f in ("perm", "pos", "mass") else
+                    v[:(nb0 + nb1 if f == "bucket_cell" else nc0 + nc1)]) for f, v in A.items()}
+        return DeviceTree(**trim, box_L=kf.box_L, n_cell_first=nc0, grouped=True)
 
     def lists_build(self, dtree, theta: float, eps: float, sinks: str = "all",
                     n_images: Optional[int] = None):

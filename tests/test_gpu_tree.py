@@ -181,6 +181,49 @@ def test_device_forest_equals_oracle_forest(mg_ctx, name, frac):
     assert np.all(ag[:n0] == -7.0)
 
 
+@pytest.mark.parametrize("name,frac", [("clustered_16", 0.1), ("lattice_12", 0.03)])
+def test_kept_fixed_tree_equals_one_call_forest(mg_ctx, name, frac):
+    """Sec. 3.2: the fixed tree built once and the very active tree rebuilt
+    alone behind it give, array for array, the forest of one call; again
+    after the very active particles have moved (the fixed ones kept)."""
+    mg, ctx = mg_ctx
+    ps = SETS[name]()
+    rng = np.random.default_rng(29)
+    g = np.zeros(ps.n, np.uint8)
+    g[rng.choice(ps.n, max(2, int(frac * ps.n)), replace=False)] = 1
+    pos = ps.pos.copy()
+    fields = ("perm", "pos", "mass", "cell_first", "cell_count", "child", "com", "bmax", "bbox",
+              "mom", "bucket_cell")
+    _case(f"kept fixed tree {name} n={ps.n} very active={int(g.sum())}")
+    kf = ctx.forest_keep(_dev(pos, np.float64), _dev(ps.mass, np.float64), ps.box_L, _dev(g))
+    for step in range(2):
+        if step:  # the very active particles move, the fixed tree stays
+            sel = g == 1
+            pos[sel] = np.mod(pos[sel] + rng.normal(0, 0.01, (int(sel.sum()), 3)), ps.box_L)
+            pos[pos >= ps.box_L] = 0.0
+        _case(f"kept fixed tree {name} rebuild {step}")
+        tk = ctx.forest_rebuild(kf, _dev(pos, np.float64), _dev(ps.mass, np.float64))
+        tf = ctx.tree_build(_dev(pos, np.float64), _dev(ps.mass, np.float64), ps.box_L, 16,
+                            group_dev=_dev(g))
+        assert tk.n_cell_first == tf.n_cell_first and tk.roots == tf.roots
+        for f in fields:
+            a, b = getattr(tk, f).cpu().numpy(), getattr(tf, f).cpu().numpy()
+            assert a.shape == b.shape and np.array_equal(a, b), f"{f} (rebuild {step})"
+        lk = ctx.lists_build(tk, 0.7, ps.eps, sinks="second").to_host()
+        lf = ctx.lists_build(tf, 0.7, ps.eps, sinks="second").to_host()
+        for f in ("pp_off", "pc_off", "pp_src", "pp_img", "pc_src", "pc_img"):
+            assert np.array_equal(getattr(lk, f), getattr(lf, f)), f
+    with pytest.raises(ValueError):
+        ctx.forest_keep(_dev(pos, np.float64), _dev(ps.mass, np.float64), 0.0, _dev(g))
+    _case("tree offset: fewer ids than particles is rejected")
+    t1 = ctx.tree_build(_dev(pos[:100], np.float64), _dev(ps.mass[:100], np.float64), ps.box_L)
+    f1 = {f: getattr(t1, f) for f in fields}
+    with pytest.raises(mg.MgravError) as e:
+        ctx._tree_offset(f1, t1.cell_first.shape[0], t1.bucket_cell.shape[0], 100, 0, 0,
+                         _dev(np.arange(50, dtype=np.int64)))
+    assert e.value.status == mg.ERR_INVALID_ARG
+
+
 def test_device_tree_errors(mg_ctx):
     mg, ctx = mg_ctx
     ps = workloads.perturbed_lattice(8, 0.2, seed=5)
