@@ -304,6 +304,12 @@ mgrav_status mgrav_store_permute(mgrav_ctx *ctx, int64_t n, const mgrav_store *i
  * coordinate leaves the grid). */
 mgrav_status mgrav_store_drift(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, double dt,
                                int periodic);
+/* The same drift for the particles on rungs rung_lo <= rung < rung_hi
+ * only (Sec. 3.2: the fixed particles drift to the middle of the fixed
+ * rung's step and from there to its end, the very active ones substep by
+ * substep).  INVALID_ARG also for a range outside 0 .. 256. */
+mgrav_status mgrav_store_drift_rungs(mgrav_ctx *ctx, int64_t n, const mgrav_store *st, double dt,
+                                     int periodic, int rung_lo, int rung_hi);
 /* Half kick of the particles on rungs >= rung_lo: v += a dt_base / 2^(rung+1),
  * acc [3][n] float SoA (device, as mgrav_compute writes it), in double and
  * rounded to float once. */

@@ -147,6 +147,90 @@ def base_step(state: State, forces: Callable, eps: float, eta: float, dt_base: f
     return s
 
 
+def fixed_rung(rung: np.ndarray, k: int, rung_max: int, dual_below: float):
+    """Sec. 3.2's fixed rung for an interval starting at substep boundary k:
+    the shallowest r in 1 .. rung_max - 1 such that k is a step boundary of
+    rung r - 1 (k a multiple of 2^(rung_max - r + 1)) and the particles on
+    rungs >= r (the very active ones) are some, but fewer than dual_below
+    of all; None if there is none.  r <= rung_max - 1 keeps at least two
+    rungs below the fixed rung r - 1, the condition under which the paper
+    builds the second tree.  The interval is one step of rung r - 1."""
+    n = rung.shape[0]
+    for r in range(1, rung_max):
+        if k % (1 << (rung_max - r + 1)):
+            continue
+        m = int(np.count_nonzero(rung >= r))
+        if 0 < m < dual_below * n:
+            return r
+    return None
+
+
+def base_step_fixed(state: State, forces: Callable, eps: float, eta: float, dt_base: float,
+                    rung_max: int, dual_below: float, log: list | None = None) -> State:
+    """One base step with the fixed tree of Sec. 3.2.  Where an interval of
+    the fixed rung r - 1 starts (fixed_rung), the particles on rungs below r
+    (fixed: none of them is kicked inside the interval) drift half the
+    interval at once and stay there, the very active ones drift substep by
+    substep, and their forces at the substeps inside the interval are taken
+    with the fixed particles at that midpoint: forces(pos, active, group)
+    with group the very active particles (the second tree's).  At the
+    interval's end the fixed particles drift the other half and the force
+    is the usual one, forces(pos, active).  Elsewhere as base_step.  The log
+    holds (k, lowest active rung, active count, second tree used)."""
+    s = dataclasses.replace(state)
+    n = s.q.shape[0]
+    nsub = 1 << rung_max
+    tau = dt_base / nsub
+    allp = np.ones(n, bool)
+    s.vel = half_kick(s.vel, s.acc, s.rung, dt_base, allp)
+
+    def drift_sel(sel, dt):
+        q = s.q.copy()
+        q[sel] = drift(s.q[sel], s.vel[sel], dt, s.scale, s.periodic)
+        s.q = q
+
+    def force_step(k1, group):
+        lo = boundary_rung(k1, rung_max)
+        act = s.rung >= lo
+        if log is not None:
+            log.append((k1, lo, int(act.sum()), group is not None))
+        pos = decode(s.q, s.origin, s.scale)
+        acc, pot = forces(pos, act) if group is None else forces(pos, act, group)
+        s.acc = s.acc.copy()
+        s.pot = s.pot.copy()
+        s.acc[act] = acc[act]
+        s.pot[act] = pot[act]
+        s.vel = half_kick(s.vel, s.acc, s.rung, dt_base, act)
+        new = rung_of(np.linalg.norm(s.acc[act], axis=1), eps, eta, dt_base, lo, rung_max)
+        s.rung = s.rung.copy()
+        s.rung[act] = new
+        if k1 < nsub:
+            s.vel = half_kick(s.vel, s.acc, s.rung, dt_base, act)
+
+    k = 0
+    while k < nsub:
+        r = fixed_rung(s.rung, k, rung_max, dual_below)
+        if r is None:
+            drift_sel(allp, tau)
+            force_step(k + 1, None)
+            k += 1
+            continue
+        span = 1 << (rung_max - r + 1)
+        fixed = s.rung < r
+        very = ~fixed
+        half = 0.5 * span * tau
+        drift_sel(fixed, half)
+        for j in range(1, span + 1):
+            drift_sel(very, tau)
+            if j < span:
+                force_step(k + j, very)
+            else:
+                drift_sel(fixed, half)
+                force_step(k + j, None)
+        k += span
+    return s
+
+
 def energies(state: State, mass: np.ndarray):
     """Kinetic and potential energy at a base-step boundary (velocities
     synchronised, potentials of the last force computation)."""

@@ -202,6 +202,8 @@ def _declare():
     L.mgrav_store_permute.argtypes = [_P, _I64, SP, _P, SP]
     L.mgrav_store_drift.restype = _I
     L.mgrav_store_drift.argtypes = [_P, _I64, SP, _D, _I]
+    L.mgrav_store_drift_rungs.restype = _I
+    L.mgrav_store_drift_rungs.argtypes = [_P, _I64, SP, _D, _I, _I, _I]
     L.mgrav_store_kick.restype = _I
     L.mgrav_store_kick.argtypes = [_P, _I64, SP, _P, _D, _I]
     L.mgrav_store_rungs.restype = _I
@@ -237,7 +239,8 @@ EXPORTS = (
     "mgrav_tree_workspace_size", "mgrav_tree_build", "mgrav_tree_offset",
     "mgrav_lists_workspace_size",
     "mgrav_lists_count", "mgrav_lists_fill", "mgrav_store_encode", "mgrav_store_decode",
-    "mgrav_store_permute", "mgrav_store_drift", "mgrav_store_kick", "mgrav_store_rungs",
+    "mgrav_store_permute", "mgrav_store_drift", "mgrav_store_drift_rungs", "mgrav_store_kick",
+    "mgrav_store_rungs",
     "mgrav_store_active", "mgrav_fmm_lists_count_host", "mgrav_fmm_lists_fill_host",
     "mgrav_fmm_workspace_size", "mgrav_fmm_apply",
 )
@@ -823,6 +826,15 @@ class Context:
         s = st.c()
         _check(_lib.mgrav_store_drift(self._h, st.n, ctypes.byref(s), float(dt),
                                       int(bool(periodic))), self._h)
+
+    def store_drift_rungs(self, st: "ParticleStore", dt: float, periodic: bool, rung_lo: int,
+                          rung_hi: int):
+        """Drift of the particles on rungs rung_lo <= rung < rung_hi only."""
+        self._sync_in()
+        s = st.c()
+        _check(_lib.mgrav_store_drift_rungs(self._h, st.n, ctypes.byref(s), float(dt),
+                                            int(bool(periodic)), int(rung_lo), int(rung_hi)),
+               self._h)
 
     def store_kick(self, st: "ParticleStore", acc_dev, dt_base: float, rung_lo: int):
         self._sync_in()

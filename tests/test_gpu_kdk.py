@@ -188,6 +188,63 @@ def test_kdk_periodic_lattice_matches_the_oracle(mg_ctx):
     assert d.max() < 1e-6 and dv < 1e-4
 
 
+def test_kdk_fixed_tree_matches_the_oracle(mg_ctx):
+    """Sec. 3.2 with the fixed tree kept: clustered 12^3 (periodic, exact
+    Ewald) from rest, rungs 0..4 with 3 % on rung 3, so that intervals of
+    rung 2 open; the device (fixed tree built once per interval, very
+    active tree rebuilt behind it) against oracle/kdk.base_step_fixed
+    with the oracle's forest, one base step."""
+    mg, ctx = mg_ctx
+    from paper_1609_08621_amd.kdk import Integrator
+    ps = workloads.make(3, scale_n1d=12)
+    t = oracle.build_tree(ps.pos, ps.mass, ps.box_L, 16)
+    a, _ = oracle.evaluate(t, oracle.build_lists(t, 0.7, ps.eps), ps.pos[t.perm],
+                           ps.mass[t.perm], ps.eps, 7)
+    am = np.zeros(ps.n)
+    am[t.perm] = np.linalg.norm(a, axis=1)
+    R = 4
+    dt = float(np.quantile(0.2 * np.sqrt(ps.eps / am), 0.03)) * 4 * 1.0001
+    origin, scale = (0.0, 0.0, 0.0), 1.0 / 2 ** 32
+    vel = np.zeros((ps.n, 3), np.float32)
+    _case(f"kdk fixed tree clustered_12: device, 1 base step of 2^{R} substeps, dt {dt:.4g}")
+    it = Integrator(ctx, _dev(ps.pos), _dev(vel), ps.mass[0], ps.eps, 0.7, 1.0, dt, R,
+                    origin=origin, scale=scale, dual_mode="fixed")
+    it.start()
+    it.base_step()
+    _case("kdk fixed tree clustered_12: oracle")
+    f0 = _oracle_forces(ps.mass, ps.eps, 0.7, 1.0, it.dual_below)
+
+    def f(pos, active, group=None):
+        if group is None:
+            return f0(pos, active)
+        tr = oracle.build_forest(pos, ps.mass, 1.0, group.astype(np.uint8))
+        sinks = np.flatnonzero(tr.bucket_cell >= tr.roots[1])
+        lists = oracle.build_lists(tr, 0.7, ps.eps, sinks=sinks)
+        tr = dataclasses.replace(tr, bucket_cell=np.ascontiguousarray(tr.bucket_cell[sinks]))
+        a_t, p_t = oracle.evaluate(tr, lists, pos[tr.perm], ps.mass[tr.perm], ps.eps, 7)
+        acc, pot = np.zeros((len(ps.mass), 3)), np.zeros(len(ps.mass))
+        acc[tr.perm] = a_t
+        pot[tr.perm] = p_t
+        return acc, pot
+    so = kdk.State(kdk.quantize(ps.pos, origin, scale, True), vel, np.zeros(ps.n, np.int64),
+                   None, None, origin, scale, True)
+    so = kdk.start(so, f, ps.eps, 0.2, dt, R)
+    log = []
+    so = kdk.base_step_fixed(so, f, ps.eps, 0.2, dt, R, it.dual_below, log)
+    pos_d, vel_d, rung_d, _, _ = [x.cpu().numpy() for x in it.state()]
+    print(f"  rungs {np.bincount(rung_d, minlength=R + 1)}; kept-tree substeps {it.kept}; "
+          f"log {it.log}", flush=True)
+    assert [(k, lo, n) for (k, lo, n, _) in it.log] == [(k, lo, n) for (k, lo, n, _) in log]
+    assert it.kept and it.kept == [k for (k, _, _, g) in log if g]
+    assert np.array_equal(rung_d, so.rung)
+    x_or = kdk.decode(so.q, origin, scale)
+    d = np.abs(pos_d - x_or)
+    d = np.minimum(d, 1.0 - d)
+    dv = np.abs(vel_d - so.vel).max() / np.sqrt(np.mean(so.vel.astype(np.float64) ** 2))
+    print(f"  max |dx| {d.max():.3e}, max |dv|/v_rms {dv:.3e}", flush=True)
+    assert d.max() < 1e-6 and dv < 1e-4
+
+
 def test_store_positions_give_identical_forces(mg_ctx):
     """The 64^3 lattice on the 2^32 grid of the unit box: the evaluation
     reading positions from the store (12 bytes, equal masses without an

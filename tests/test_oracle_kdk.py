@@ -148,3 +148,80 @@ def test_individual_time_steps_conserve_energy_on_a_plummer_sphere():
     # force computations follow the schedule: at boundary k the rungs >= l_k
     assert [lo for (_, lo, _) in log[:16]] == [kdk.boundary_rung(k, R) for k in range(1, 17)]
     assert all(cnt == ps.n for (k, lo, cnt) in log if lo == 0)
+
+
+def test_fixed_rung_rule():
+    """Sec. 3.2: the second tree for the rungs below the shallowest rung
+    whose particles, with the deeper ones, are fewer than 5 %, at a step
+    boundary of the rung above it, with two rungs below the fixed one."""
+    R = 4
+    r = np.array([0] * 96 + [3] * 4)
+    assert kdk.fixed_rung(r, 0, R, 0.05) == 1     # 4 % on rungs >= 1: the whole base step
+    assert kdk.fixed_rung(r, 8, R, 0.05) == 2     # mid-step: a boundary of rung 1, not 0
+    assert kdk.fixed_rung(r, 4, R, 0.05) == 3
+    assert kdk.fixed_rung(r, 6, R, 0.05) is None  # a boundary of rung 3 only
+    r = np.array([0] * 50 + [1] * 46 + [3] * 4)
+    assert kdk.fixed_rung(r, 0, R, 0.05) == 2     # rungs >= 1 hold half
+    assert kdk.fixed_rung(r, 8, R, 0.05) == 2
+    assert kdk.fixed_rung(r, 4, R, 0.05) == 3     # a boundary of rung 2 only
+    assert kdk.fixed_rung(r, 2, R, 0.05) is None  # of rung 3 only: one rung below
+    r = np.array([0] * 50 + [3] * 48 + [4] * 2)
+    assert kdk.fixed_rung(r, 0, R, 0.05) is None  # only the deepest rung is small
+    assert kdk.fixed_rung(np.zeros(100, np.int64), 0, R, 0.05) is None
+    assert kdk.fixed_rung(np.array([0] * 99 + [2]), 0, R, 0.0) is None
+
+
+def _plummer_512():
+    import workloads
+    ps = workloads.plummer(512, seed=5, eps=0.05, fp32_positions=False)
+    origin, scale = (-60.0, -60.0, -60.0), 120.0 / kdk.TWO32
+    rng = np.random.default_rng(2)
+    _, pot = oracle.direct_open(ps.pos, ps.mass, ps.eps)
+    v = np.sqrt(np.maximum(-pot, 0) / 3.0)[:, None] * rng.normal(size=(ps.n, 3)) * 0.7
+    st = kdk.State(kdk.quantize(ps.pos, origin, scale, False), v.astype(np.float32),
+                   np.zeros(ps.n, np.int64), None, None, origin, scale, False)
+    return ps, st
+
+
+def _direct3(mass, eps):
+    f = _direct(mass, eps)
+    return lambda pos, active, group=None: f(pos, active)
+
+
+def test_fixed_schedule_without_intervals_is_the_plain_step():
+    ps, st = _plummer_512()
+    f = _direct3(ps.mass, ps.eps)
+    st = kdk.start(st, f, ps.eps, 0.2, 0.25, 4)
+    a = kdk.base_step(st, f, ps.eps, 0.2, 0.25, 4)
+    b = kdk.base_step_fixed(st, f, ps.eps, 0.2, 0.25, 4, 0.0)
+    for x, y in ((a.q, b.q), (a.vel, b.vel), (a.rung, b.rung), (a.acc, b.acc)):
+        assert np.array_equal(x, y)
+
+
+def test_fixed_tree_intervals_conserve_energy_and_track_the_plain_step():
+    """Plummer 512 with rungs 0..4, 3 % on rung 3: intervals of rung 2 with
+    the fixed particles at their midpoint.  The fixed particles end each
+    interval where substep drifts put them (to a few grid steps, the
+    rounding of 2 drifts against 4), the very active ones stay within the
+    midpoint approximation of the plain trajectories, and energy is
+    conserved as with the plain schedule."""
+    ps, st0 = _plummer_512()
+    f = _direct3(ps.mass, ps.eps)
+    R, dt = 4, 0.25
+    st0 = kdk.start(st0, f, ps.eps, 0.2, dt, R)
+    e0 = sum(kdk.energies(st0, ps.mass))
+    log = []
+    a = kdk.base_step_fixed(st0, f, ps.eps, 0.2, dt, R, 0.05, log)
+    b = kdk.base_step(st0, f, ps.eps, 0.2, dt, R)
+    used = [k for (k, lo, cnt, g) in log if g]
+    assert used, "no interval opened"
+    assert all(lo >= 3 for (k, lo, cnt, g) in log if g)
+    assert [lo for (_, lo, _, _) in log] == [kdk.boundary_rung(k, R) for k in range(1, 17)]
+    fixed = st0.rung < 3  # rungs are shallower than 3 at the start: fixed in every interval
+    dq = np.abs(a.q - b.q)
+    assert dq[~fixed].max() > 0  # the approximation changes the very active orbits ...
+    x_a = kdk.decode(a.q, a.origin, a.scale)
+    x_b = kdk.decode(b.q, b.origin, b.scale)
+    assert np.abs(x_a - x_b).max() < 1e-3  # ... a little
+    e1 = sum(kdk.energies(a, ps.mass))
+    assert abs(e1 - e0) < 2e-3 * abs(e0)
