@@ -444,6 +444,38 @@ def test_edge_cases(mg_ctx):
         assert np.abs(pg - po).max() <= 1e-5 * (1 + np.abs(po).max()), name
 
 
+def test_empty_and_single_particle_masks(mg_ctx):
+    """A mask with no active particle leaves every output as it was and
+    reports no work; a mask with one active particle (an inner one, then
+    the last particle) gives it the bits of the full run.  Each compute
+    stages for its own mask (a bind before each)."""
+    mg, ctx = mg_ctx
+    ps = workloads.make(3, scale_n1d=20)
+    tree, lists, pos_t, mass_t = prepared(ps)
+    _case(f"masks with 0 and 1 active particles, clustered_20 n={ps.n}: full run")
+    a_full, p_full, _ = gpu(mg_ctx, ps, tree, lists, pos_t, mass_t)
+    dev = torch.device("cuda", 0)
+    for label, idx in (("no particle", []), ("particle 1234", [1234]),
+                       ("the last particle", [ps.n - 1])):
+        _case(f"mask with {label} active")
+        act = np.zeros(ps.n, np.uint8)
+        act[idx] = 1
+        tensors, p = ctx.upload(pos_t, mass_t, tree, lists, ps.eps, 0.7)
+        ctx.bind(p, tensors)
+        ctx.set_active(torch.from_numpy(act).to(dev))
+        acc = torch.full((3 * ps.n,), -7.0, dtype=torch.float32, device=dev)
+        pot = torch.full((ps.n,), -7.0, dtype=torch.float32, device=dev)
+        ctx.compute(acc, pot)
+        st = ctx.wait(120)
+        ctx.set_active(None)
+        ag = acc.cpu().numpy().reshape(3, -1).T
+        pg = pot.cpu().numpy()
+        assert st.n_active_particles == len(idx)
+        on = act == 1
+        assert np.all(ag[~on] == -7.0) and np.all(pg[~on] == -7.0)
+        assert np.array_equal(ag[on], a_full[on]) and np.array_equal(pg[on], p_full[on])
+
+
 def test_bad_list_entry_is_reported_not_dereferenced(mg_ctx):
     mg, ctx = mg_ctx
     ps = workloads.plummer(2000, seed=5)
