@@ -207,7 +207,8 @@ mgrav_status mgrav_tree_build(mgrav_ctx *ctx, int64_t n, const double *pos, cons
  * the particles ids[0 .. n_particles-1] of a forest's input (device int64,
  * in input order), into one tree of that forest, in place: cell_first +=
  * particle_offset, child (where >= 0) and bucket_cell += cell_offset,
- * perm[i] = ids[perm[i]].  The arrays of `t` are device memory, sized
+ * perm[i] = ids[perm[i]] (ids NULL: the subset is the input range from
+ * particle_offset, perm[i] += particle_offset).  The arrays of `t` are device memory, sized
  * n_cell (cell_first, child), n_bucket (bucket_cell) and n_particles
  * (perm).  Built this way into consecutive ranges of one set of arrays
  * (the group-0 particles with offsets 0, then the others with offsets

@@ -673,7 +673,8 @@ class Context:
         td = TreeDev(*[views[f].data_ptr() for f, _ in TreeDev._fields_])
         _check(_lib.mgrav_tree_offset(self._h, ctypes.byref(td), int(n_cell), int(n_bucket),
                                       int(n_part), int(cell_offset), int(particle_offset),
-                                      _P(ids.data_ptr()), int(ids.numel())), self._h)
+                                      _P(ids.data_ptr()) if ids is not None else None,
+                                      int(ids.numel()) if ids is not None else 0), self._h)
 
     def forest_keep(self, pos_dev, mass_dev, box_L: float, group_dev, bucket: int = 16):
         """The fixed tree of Sec. 3.2 built once: the tree of the group-0

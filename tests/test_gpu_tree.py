@@ -215,9 +215,16 @@ def test_kept_fixed_tree_equals_one_call_forest(mg_ctx, name, frac):
             assert np.array_equal(getattr(lk, f), getattr(lf, f)), f
     with pytest.raises(ValueError):
         ctx.forest_keep(_dev(pos, np.float64), _dev(ps.mass, np.float64), 0.0, _dev(g))
-    _case("tree offset: fewer ids than particles is rejected")
+    _case("tree offset: without ids the subset is a range; fewer ids than particles is rejected")
     t1 = ctx.tree_build(_dev(pos[:100], np.float64), _dev(ps.mass[:100], np.float64), ps.box_L)
     f1 = {f: getattr(t1, f) for f in fields}
+    before = {f: v.cpu().numpy().copy() for f, v in f1.items()}
+    ctx._tree_offset(f1, t1.cell_first.shape[0], t1.bucket_cell.shape[0], 100, 5, 7, None)
+    after = {f: v.cpu().numpy() for f, v in f1.items()}
+    assert np.array_equal(after["perm"], before["perm"] + 7)
+    assert np.array_equal(after["cell_first"], before["cell_first"] + 7)
+    assert np.array_equal(after["bucket_cell"], before["bucket_cell"] + 5)
+    assert np.array_equal(after["child"], np.where(before["child"] >= 0, before["child"] + 5, -1))
     with pytest.raises(mg.MgravError) as e:
         ctx._tree_offset(f1, t1.cell_first.shape[0], t1.bucket_cell.shape[0], 100, 0, 0,
                          _dev(np.arange(50, dtype=np.int64)))
