@@ -1404,33 +1404,36 @@ __constant__ int c_ax4[15][4] = {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 2}, {0, 0
 
 #include "erfcx_poly.inc"
 
-// 1/(2j + 11) and 1/(j + 1) for the power series, 1/(2n + 1) for the
-// downward recurrence: constants, so the loops below divide nothing.
-struct EwaldConsts {
-    double inv_odd[30];   // 1 / (2j + 11)
-    double inv_next[30];  // 1 / (j + 1)
-    double inv_2n1[6];    // 1 / (2n + 1)
-};
-__constant__ EwaldConsts c_ew = {
-    {1.0 / 11, 1.0 / 13, 1.0 / 15, 1.0 / 17, 1.0 / 19, 1.0 / 21, 1.0 / 23, 1.0 / 25, 1.0 / 27,
-     1.0 / 29, 1.0 / 31, 1.0 / 33, 1.0 / 35, 1.0 / 37, 1.0 / 39, 1.0 / 41, 1.0 / 43, 1.0 / 45,
-     1.0 / 47, 1.0 / 49, 1.0 / 51, 1.0 / 53, 1.0 / 55, 1.0 / 57, 1.0 / 59, 1.0 / 61, 1.0 / 63,
-     1.0 / 65, 1.0 / 67, 1.0 / 69},
-    {1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,
-     1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18,
-     1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
-     1.0 / 28, 1.0 / 29, 1.0 / 30},
-    {1.0 / 1, 1.0 / 3, 1.0 / 5, 1.0 / 7, 1.0 / 9, 1.0 / 11}};
+// The power series of the near images' g_5 in Horner form: coefficient j
+// is (-1)^j / (j! (2j + 11)) (the factorial an exact integer literal, one
+// rounding each); 26 terms reach double precision for x <= 2.  And
+// 1/(2n + 1) for the downward recurrence: constants, so the loops below
+// divide nothing.
+constexpr int kEwSeriesTerms = 26;
+__constant__ double c_ew_series[kEwSeriesTerms] = {
+    1.0 / (1.0 * 11), -1.0 / (1.0 * 13),
+    1.0 / (2.0 * 15), -1.0 / (6.0 * 17),
+    1.0 / (24.0 * 19), -1.0 / (120.0 * 21),
+    1.0 / (720.0 * 23), -1.0 / (5040.0 * 25),
+    1.0 / (40320.0 * 27), -1.0 / (362880.0 * 29),
+    1.0 / (3628800.0 * 31), -1.0 / (39916800.0 * 33),
+    1.0 / (479001600.0 * 35), -1.0 / (6227020800.0 * 37),
+    1.0 / (87178291200.0 * 39), -1.0 / (1307674368000.0 * 41),
+    1.0 / (20922789888000.0 * 43), -1.0 / (355687428096000.0 * 45),
+    1.0 / (6402373705728000.0 * 47), -1.0 / (121645100408832000.0 * 49),
+    1.0 / (2432902008176640000.0 * 51), -1.0 / (51090942171709440000.0 * 53),
+    1.0 / (1124000727777607680000.0 * 55), -1.0 / (25852016738884976640000.0 * 57),
+    1.0 / (620448401733239439360000.0 * 59), -1.0 / (15511210043330985984000000.0 * 61)};
+__constant__ double c_ew_inv_2n1[6] = {1.0 / 1, 1.0 / 3, 1.0 / 5, 1.0 / 7, 1.0 / 9, 1.0 / 11};
 
 // Constants of the radial functions, written by k_ewald_setup after the
 // k-space rows and read per image through scalar loads (kept in memory so
 // that they do not occupy vector registers across the image loop).
 constexpr int kEwCoef = 64 + 8 * kMaxHalfK;
-constexpr int kEwInvOdd = 0;      // 1 / (2j + 11), j < 30
-constexpr int kEwInvNext = 30;    // 1 / (j + 1), j < 30
-constexpr int kEwInv2n1 = 60;     // 1 / (2n + 1), n < 6
-constexpr int kEwErfcx = 66;      // erfcx polynomial, kErfcxDeg + 1 values
-constexpr int kEwK = 66 + 19;     // k_m = (-2 alpha^2)^m / (alpha sqrt(pi)), m < 6
+constexpr int kEwSeries = 0;                     // the series coefficients
+constexpr int kEwInv2n1 = kEwSeries + kEwSeriesTerms;  // 1 / (2n + 1), n < 6
+constexpr int kEwErfcx = kEwInv2n1 + 6;          // erfcx polynomial, kErfcxDeg + 1 values
+constexpr int kEwK = kEwErfcx + 19;              // k_m = (-2 alpha^2)^m / (alpha sqrt(pi)), m < 6
 constexpr int kEwG5 = kEwK + 6;   // 2 alpha / sqrt(pi) (-32 alpha^10)
 constexpr int kEwAl2 = kEwG5 + 1; // alpha^2
 constexpr int kEwTs = kEwAl2 + 1; // (2 / alpha) kErfcxScale
@@ -1545,11 +1548,8 @@ __global__ void __launch_bounds__(kSetupThreads) k_ewald_setup(EwaldArgs a) {
     // constants of the radial functions
     double* cf = a.table + kEwCoef;
     const int t = threadIdx.x;
-    if (t < 30) {
-        cf[kEwInvOdd + t] = c_ew.inv_odd[t];
-        cf[kEwInvNext + t] = c_ew.inv_next[t];
-    }
-    if (t < 6) cf[kEwInv2n1 + t] = c_ew.inv_2n1[t];
+    if (t < kEwSeriesTerms) cf[kEwSeries + t] = c_ew_series[t];
+    if (t < 6) cf[kEwInv2n1 + t] = c_ew_inv_2n1[t];
     if (t <= kErfcxDeg) cf[kEwErfcx + t] = c_erfcx[t];
     if (t == 0) {
         const double SQRT_PI = 1.77245385090551602729;
@@ -1587,12 +1587,9 @@ template <typename C>
 __device__ __forceinline__ void ewald_radial_near(const C& c, double r2, double E, double g[6]) {
     const double x = c[kEwAl2] * r2;
     if (x < 2.0) {
-        double sum = 0.0, term = 1.0;
+        double sum = c[kEwSeries + kEwSeriesTerms - 1];
 #pragma unroll
-        for (int j = 0; j < 30; ++j) {
-            sum = fma(term, c[kEwInvOdd + j], sum);
-            term *= -x * c[kEwInvNext + j];
-        }
+        for (int j = kEwSeriesTerms - 2; j >= 0; --j) sum = fma(sum, x, c[kEwSeries + j]);
         g[5] = c[kEwG5] * sum;
 #pragma unroll
         for (int n = 4; n >= 0; --n)
@@ -1650,9 +1647,8 @@ struct RadialConstsLocal {
         ts = (2.0 / al) * kErfcxScale;
     }
     __device__ double operator[](int i) const {
-        if (i < kEwInvNext) return c_ew.inv_odd[i - kEwInvOdd];
-        if (i < kEwInv2n1) return c_ew.inv_next[i - kEwInvNext];
-        if (i < kEwErfcx) return c_ew.inv_2n1[i - kEwInv2n1];
+        if (i < kEwInv2n1) return c_ew_series[i - kEwSeries];
+        if (i < kEwErfcx) return c_ew_inv_2n1[i - kEwInv2n1];
         if (i < kEwK) return c_erfcx[i - kEwErfcx];
         if (i < kEwG5) return kk[i - kEwK];
         if (i == kEwG5) return g5;
