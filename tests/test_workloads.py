@@ -59,3 +59,35 @@ def test_config_shapes_and_active_sets():
     assert set(np.flatnonzero(m)) == {0, 2, 5}  # the largest |a|
     assert workloads.active_by_acceleration(a, 0.0).sum() == 0
     assert workloads.active_by_acceleration(a, 1.0).sum() == 6
+
+
+def test_plummer_recipe():
+    ps = workloads.make(1)
+    assert ps.n == 8192 and ps.box_L == 0.0 and ps.eps == 0.01
+    assert np.allclose(ps.mass, 1.0 / 8192)
+    # positions are float32 values
+    assert np.array_equal(ps.pos, ps.pos.astype(np.float32).astype(np.float64))
+    r = np.linalg.norm(ps.pos, axis=1)
+    assert r.max() <= 10.0 * (1 + 1e-6)
+    # enclosed-mass fraction of a Plummer sphere truncated at 10 a:
+    # M(<r) = r^3 / (1 + r^2)^(3/2), normalised by M(<10)
+    m10 = 1000.0 / 101.0 ** 1.5
+    for rr in (0.5, 1.0, 2.0, 5.0):
+        want = rr ** 3 / (1 + rr * rr) ** 1.5 / m10
+        assert abs(np.mean(r < rr) - want) < 0.02
+    # isotropic: centre of mass near the origin, equal second moments
+    assert np.all(np.abs(ps.pos.mean(0)) < 0.1)
+    m2 = (ps.pos ** 2).mean(0)
+    assert np.all(np.abs(m2 / m2.mean() - 1) < 0.15)
+
+
+def test_clustered_halo_radii_scale_with_config():
+    # the 512^3 recipe has haloes a quarter the size of the 128^3 one: the
+    # same scaled-down set is more concentrated
+    a = workloads.clustered(24, 40, seed=5)
+    b = workloads.clustered(24, 40, seed=5, a_max=0.005 / 4.0)
+    def top_share(ps):
+        k = np.floor(ps.pos * 64).astype(int)
+        occ = np.bincount((k[:, 0] * 64 + k[:, 1]) * 64 + k[:, 2], minlength=64 ** 3)
+        return np.sort(occ)[::-1][:64 ** 3 // 1000].sum() / ps.n
+    assert top_share(b) > top_share(a)
