@@ -37,3 +37,13 @@ def test_stale_or_foreign_counters_read_as_unmeasured(tmp_path, monkeypatch):
     (prof / os.path.basename(src)).write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "counters_file", lambda wl: str(prof / os.path.basename(src)))
     assert bench.interact_traffic("clustered_512cubed_periodic", 32, 3, False) is None
+
+
+def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
+    # one GPU only: the run ends with a message and status 2 before any
+    # device work
+    monkeypatch.setattr("sys.argv", ["bench.py", "--gpus", "2"])
+    with pytest.raises(SystemExit) as e:
+        bench.main()
+    assert e.value.code == 2
+    assert "exactly one GPU" in capsys.readouterr().err
