@@ -219,3 +219,14 @@ def test_host_fmm_lists_equal_oracle(sets, k):
               "cc_src", "cc_img"):
         assert np.array_equal(getattr(lg, f), getattr(lo, f)), f
     assert lo.cc_src.size > 0 and (lo.cc_src < 0).any() and (lo.pp_sub > 0).any()
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: with the HIP library absent the binding does not import."""
+    import subprocess
+    import sys
+    env = dict(os.environ, MGRAV_LIBRARY=str(tmp_path / "libmgrav_absent.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_1609_08621_amd"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "no fallback" in r.stderr
